@@ -1,0 +1,194 @@
+/*
+ * spgemm.h — C ABI of the MI355X (gfx950) hash-table SpGEMM library.
+ *
+ * Operation: C = A*B for sparse A (m x n) and B (n x k) in CSR, over the
+ * (+, x) semiring on IEEE binary64 or on int64 (wrap-around), as defined by
+ * Gustavson's row-wise algorithm (paper Section 2, Fig. 1).  The library runs
+ * the two-phase method of the paper (Section 2 "two-phase method"; Hash
+ * SpGEMM driver, Section 4.2.1, Fig. 5):
+ *
+ *   spgemm_plan      row flop count (Section 4.1, Fig. 4 part 1) and the
+ *                    grouping of rows by flop (the GPU counterpart of the
+ *                    flop-balanced partition of Fig. 4 part 2); returns the
+ *                    workspace size.
+ *   spgemm_symbolic  per-row nnz of C from hash-table (or bitmap) insertion of
+ *                    keys only (Section 4.2.1), prefix-summed into the int64
+ *                    row pointers of C; returns nnz(C) to the host.
+ *   spgemm_numeric   accumulation of a_ik*b_kj into hash tables and compaction
+ *                    into the caller's columns/values of C; each row sorted by
+ *                    column when SPGEMM_SORTED is set (Section 4.2.1, output
+ *                    step), otherwise in table order.
+ *   spgemm_free      releases the plan's host-side state.
+ *
+ * Memory ownership: the library never allocates device memory.  Every device
+ * buffer (plan scratch, workspace, C) comes from the caller and must stay
+ * allocated and unmodified (except for the documented outputs) until the
+ * plan is freed.  The plan object itself is host memory owned by the library.
+ *
+ * Streams: all device work is enqueued on the stream given to spgemm_plan.
+ * spgemm_plan and spgemm_symbolic synchronise that stream (they read a few
+ * bytes of results back to the host); spgemm_numeric does not.
+ *
+ * Errors: every function returns SPGEMM_OK (0) or a negative status; nothing
+ * aborts and no C++ exception crosses the ABI.  spgemm_strerror() gives the
+ * text; for SPGEMM_ERR_HIP it includes the HIP runtime's message.
+ */
+#ifndef SPGEMM_H
+#define SPGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Value type of A, B and C (all three share it). */
+typedef enum {
+    SPGEMM_F64 = 0, /* IEEE binary64; sums within 1e-12 relative of any order */
+    SPGEMM_I64 = 1  /* int64, multiply and add modulo 2^64 (exact)            */
+} spgemm_dtype;
+
+/* Flags for spgemm_plan. */
+enum {
+    SPGEMM_SORTED = 1u << 0,   /* emit each row of C with ascending column ids     */
+    SPGEMM_VALIDATE = 1u << 1  /* check A and B structure on the device at plan time
+                                  (row pointers non-decreasing from 0 to nnz, column
+                                  ids in range); failure gives SPGEMM_ERR_INVALID_CSR */
+};
+
+/* Status codes. */
+enum {
+    SPGEMM_OK = 0,
+    SPGEMM_ERR_INVALID_ARG = -1,  /* NULL pointer, negative size, bad dtype/flags     */
+    SPGEMM_ERR_SHAPE = -2,        /* A.ncols != B.nrows                               */
+    SPGEMM_ERR_INVALID_CSR = -3,  /* SPGEMM_VALIDATE found malformed A or B           */
+    SPGEMM_ERR_WORKSPACE = -4,    /* workspace pointer NULL while bytes are needed    */
+    SPGEMM_ERR_OVERFLOW = -5,     /* a size exceeds the supported index range         */
+    SPGEMM_ERR_STATE = -6,        /* calls out of order (e.g. numeric before symbolic) */
+    SPGEMM_ERR_HIP = -7,          /* a HIP runtime call failed                         */
+    SPGEMM_ERR_UNSUPPORTED = -8,  /* input outside the supported envelope              */
+    SPGEMM_ERR_HOST_ALLOC = -9,   /* host memory for the plan could not be allocated   */
+    SPGEMM_ERR_INTERNAL = -10     /* a device-side consistency check failed            */
+};
+
+/*
+ * A CSR operand (paper Section 2, CSR paragraph).  All pointers are DEVICE
+ * pointers, owned by the caller, read-only to the library:
+ *   rpts  int32[nrows + 1], rpts[0] = 0, non-decreasing, rpts[nrows] = nnz
+ *   cols  int32[nnz], 0 <= cols[p] < ncols, any order within a row
+ *   vals  nnz values of the plan's dtype (may be NULL until spgemm_numeric)
+ * Limits: nrows, ncols < 2^31 - 1, nnz < 2^31 - 1.  Repeated column ids in a
+ * row are allowed and simply add up.
+ */
+typedef struct {
+    int64_t nrows;
+    int64_t ncols;
+    int64_t nnz;
+    const int32_t *rpts;
+    const int32_t *cols;
+    const void *vals;
+} spgemm_csr;
+
+typedef struct spgemm_plan_s *spgemm_plan_t;
+
+/*
+ * Bytes of device "plan scratch" spgemm_plan needs for nprod products whose
+ * left operands are A[0..nprod-1] (per-row flop counts plus a small header).
+ * Returns 0 if an argument is invalid.
+ */
+size_t spgemm_plan_scratch_bytes(int nprod, const spgemm_csr *A);
+
+/*
+ * Plan nprod independent products C[p] = A[p]*B[p] (nprod >= 1; A and B are
+ * host arrays of nprod descriptors).  Computes row flop and groups rows by
+ * flop on the device, then reads the group sizes back (synchronises stream).
+ *   plan_scratch     device buffer of spgemm_plan_scratch_bytes(nprod, A)
+ *                    bytes, kept alive until spgemm_free
+ *   workspace_bytes  out: bytes of device workspace spgemm_symbolic needs
+ * Values are not read here.  On error *out is NULL.
+ */
+int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm_csr *B,
+                spgemm_dtype dtype, unsigned flags, void *plan_scratch, hipStream_t stream,
+                size_t *workspace_bytes);
+
+/*
+ * Symbolic phase.  Writes rpts_C[p][0..A[p].nrows] (device int64, caller-owned,
+ * nrows+1 entries each; rpts_C is a host array of nprod device pointers) and
+ * stores nnz(C[p]) in nnz_C[p] (host array of nprod).  Synchronises stream.
+ *   workspace  device buffer of the size spgemm_plan returned, kept alive
+ *              until spgemm_free
+ */
+int spgemm_symbolic(spgemm_plan_t plan, void *workspace, int64_t *const *rpts_C, int64_t *nnz_C);
+
+/*
+ * Numeric phase.  A and B must describe the same matrices (same pointers for
+ * rpts/cols) as at plan time; their vals must now be set (new values with the
+ * same pattern may be passed on later calls: the symbolic result is reused).
+ * cols_C[p] (device int32[nnz_C[p]]) and vals_C[p] (device dtype[nnz_C[p]])
+ * are caller-owned outputs; cols_C and vals_C are host arrays of nprod device
+ * pointers.  Asynchronous on the plan's stream.
+ */
+int spgemm_numeric(spgemm_plan_t plan, const spgemm_csr *A, const spgemm_csr *B,
+                   int32_t *const *cols_C, void *const *vals_C);
+
+/* Release the plan's host state (device buffers stay the caller's).  NULL-safe. */
+int spgemm_free(spgemm_plan_t plan);
+
+/* Static text for a status code (the HIP message for SPGEMM_ERR_HIP is that of
+ * the most recent failure in this process). */
+const char *spgemm_strerror(int status);
+
+/* Counters of one planned product, for reporting. */
+typedef struct {
+    int64_t flop;            /* multiplications a_ik*b_kj (paper Section 2)        */
+    int64_t max_row_flop;
+    int64_t nnz_C;           /* valid after spgemm_symbolic                         */
+    int64_t heavy_rows;      /* rows accumulated in column windows                  */
+    int64_t windows;         /* column-window work items of those rows              */
+    int64_t probe_overflow;  /* must be 0: hash probes that exceeded the table size */
+} spgemm_stats;
+
+int spgemm_plan_stats(spgemm_plan_t plan, int iprod, spgemm_stats *out);
+
+/*
+ * Per-kernel timing.  When enabled, the library records HIP events around
+ * each kernel launch on the plan's stream; spgemm_plan_kernel_times waits for
+ * them and reports, for each kernel name, the summed milliseconds, launch
+ * count and the algorithmic bytes that launch moves (the per-kernel byte
+ * model of the library's design notes).  Returns the number of kernels
+ * written (at most cap), or a negative status.
+ */
+typedef struct {
+    char name[48];
+    double ms;
+    int64_t launches;
+    double alg_bytes;
+} spgemm_kernel_time;
+
+int spgemm_plan_set_timing(spgemm_plan_t plan, int enable);
+int spgemm_plan_kernel_times(spgemm_plan_t plan, spgemm_kernel_time *out, int cap);
+
+/*
+ * Masked sum for triangle counting (paper Section 5.6): out[0] = sum over the
+ * stored positions (i, j) of M of C_ij, int64 wrap-around.  C has int64 row
+ * pointers (as spgemm_symbolic writes them) and int64 values; M is a CSR
+ * pattern (its vals are ignored).  Rows of C and M may be in any column order.
+ * out is a device int64 (overwritten).  Asynchronous on stream.
+ */
+int spgemm_masked_sum_i64(int64_t nrows, int64_t ncols, const int64_t *rpts_C, const int32_t *cols_C,
+                          const int64_t *vals_C, const spgemm_csr *M, int64_t *out, hipStream_t stream);
+
+/*
+ * Streaming copy of nbytes (multiple of 16) from src to dst, both device
+ * pointers: the measured HBM copy rate is the denominator the benchmark
+ * compares the SpGEMM byte rates with.  Asynchronous on stream.
+ */
+int spgemm_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPGEMM_H */
