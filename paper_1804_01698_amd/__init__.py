@@ -1,0 +1,26 @@
+"""MI355X (gfx950) hash-table SpGEMM: Python binding of ``libspgemm.so``.
+
+Only argument marshalling lives here: every step of the product runs in the HIP
+kernels of the library (``csrc/``).  PyTorch supplies device memory and the
+stream.  The binding raises ``ImportError`` when the library has not been built:
+there is no CPU fallback.
+"""
+from .binding import (
+    DeviceCSR,
+    Plan,
+    SpgemmError,
+    F64,
+    I64,
+    SORTED,
+    VALIDATE,
+    lib_path,
+    masked_sum_i64,
+    spgemm,
+    stream_copy,
+    triangle_count,
+)
+
+__all__ = [
+    "DeviceCSR", "Plan", "SpgemmError", "F64", "I64", "SORTED", "VALIDATE", "lib_path",
+    "masked_sum_i64", "spgemm", "stream_copy", "triangle_count",
+]

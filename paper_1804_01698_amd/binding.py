@@ -1,0 +1,270 @@
+"""ctypes marshalling for the C ABI declared in include/spgemm.h."""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libspgemm.so")
+
+F64, I64 = 0, 1
+SORTED, VALIDATE = 1, 2
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+class SpgemmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_lib.spgemm_strerror(status).decode()} (status {status})")
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rpts", ctypes.c_void_p), ("cols", ctypes.c_void_p), ("vals", ctypes.c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("flop", ctypes.c_int64), ("max_row_flop", ctypes.c_int64), ("nnz_C", ctypes.c_int64),
+                ("heavy_rows", ctypes.c_int64), ("windows", ctypes.c_int64),
+                ("probe_overflow", ctypes.c_int64)]
+
+
+class _KTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("ms", ctypes.c_double), ("launches", ctypes.c_int64),
+                ("alg_bytes", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(_LIB):
+        raise ImportError(f"libspgemm.so is not built ({_LIB}); run __graft_entry__.build() "
+                          "or python paper_1804_01698_amd/build.py")
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    pp = ctypes.POINTER(P)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.spgemm_plan_scratch_bytes.restype = ctypes.c_size_t
+    lib.spgemm_plan_scratch_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr)]
+    lib.spgemm_plan.restype = ctypes.c_int
+    lib.spgemm_plan.argtypes = [pp, ctypes.c_int, ctypes.POINTER(_Csr), ctypes.POINTER(_Csr), ctypes.c_int,
+                                ctypes.c_uint, P, P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.spgemm_symbolic.restype = ctypes.c_int
+    lib.spgemm_symbolic.argtypes = [P, P, pp, i64p]
+    lib.spgemm_numeric.restype = ctypes.c_int
+    lib.spgemm_numeric.argtypes = [P, ctypes.POINTER(_Csr), ctypes.POINTER(_Csr), pp, pp]
+    lib.spgemm_free.restype = ctypes.c_int
+    lib.spgemm_free.argtypes = [P]
+    lib.spgemm_strerror.restype = ctypes.c_char_p
+    lib.spgemm_strerror.argtypes = [ctypes.c_int]
+    lib.spgemm_plan_stats.restype = ctypes.c_int
+    lib.spgemm_plan_stats.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Stats)]
+    lib.spgemm_plan_set_timing.restype = ctypes.c_int
+    lib.spgemm_plan_set_timing.argtypes = [P, ctypes.c_int]
+    lib.spgemm_plan_kernel_times.restype = ctypes.c_int
+    lib.spgemm_plan_kernel_times.argtypes = [P, ctypes.POINTER(_KTime), ctypes.c_int]
+    lib.spgemm_masked_sum_i64.restype = ctypes.c_int
+    lib.spgemm_masked_sum_i64.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, ctypes.POINTER(_Csr), P, P]
+    lib.spgemm_stream_copy.restype = ctypes.c_int
+    lib.spgemm_stream_copy.argtypes = [P, P, ctypes.c_size_t, P]
+    return lib
+
+
+_lib = _load()
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise SpgemmError(st, where)
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class DeviceCSR:
+    """CSR operand resident in device memory (int32 rpts/cols; f64 or i64 vals).
+    Row pointers of products are int64 (``rpts64``) since nnz(C) may exceed 2^31."""
+    nrows: int
+    ncols: int
+    rpts: torch.Tensor                    # int32 [nrows+1] (operands) or int64 (products)
+    cols: torch.Tensor                    # int32 [nnz]
+    vals: Optional[torch.Tensor]          # float64 / int64 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.cols.numel())
+
+    @staticmethod
+    def from_host(a, device="cuda", vals=True) -> "DeviceCSR":
+        """From any object with nrows/ncols/rpts/cols/vals numpy fields."""
+        if a.nnz >= 2**31 - 1:
+            raise ValueError("operand nnz must be < 2^31 - 1")
+        rp = torch.from_numpy(np.ascontiguousarray(a.rpts, dtype=np.int32)).to(device)
+        cl = torch.from_numpy(np.ascontiguousarray(a.cols, dtype=np.int32)).to(device)
+        vv = None
+        if vals and a.vals is not None:
+            vv = torch.from_numpy(np.ascontiguousarray(a.vals)).to(device)
+        return DeviceCSR(int(a.nrows), int(a.ncols), rp, cl, vv)
+
+    def to_host(self):
+        """(rpts int64, cols int32, vals) as numpy arrays."""
+        return (self.rpts.cpu().numpy().astype(np.int64), self.cols.cpu().numpy(),
+                None if self.vals is None else self.vals.cpu().numpy())
+
+    def _c(self) -> _Csr:
+        if self.rpts.dtype != torch.int32:
+            raise TypeError("operand row pointers must be int32")
+        return _Csr(self.nrows, self.ncols, self.nnz, self.rpts.data_ptr(),
+                    self.cols.data_ptr() if self.nnz else None,
+                    self.vals.data_ptr() if (self.vals is not None and self.nnz) else None)
+
+
+def _dtype_code(A: DeviceCSR, B: DeviceCSR) -> int:
+    kinds = {t.vals.dtype for t in (A, B) if t.vals is not None}
+    if kinds <= {torch.float64}:
+        return F64
+    if kinds == {torch.int64}:
+        return I64
+    raise TypeError("values must both be float64 or both be int64")
+
+
+class Plan:
+    """One planned batch of products C[p] = A[p] @ B[p] (plan -> symbolic -> numeric).
+
+    Device buffers (plan scratch, workspace, C) are torch tensors owned here;
+    the library itself allocates no device memory."""
+
+    def __init__(self, As: Sequence[DeviceCSR], Bs: Sequence[DeviceCSR], sorted_output: bool = True,
+                 dtype: Optional[int] = None, validate: bool = False, stream=None, timing: bool = False):
+        if len(As) != len(Bs) or not As:
+            raise ValueError("need equal, non-empty lists of operands")
+        self.As, self.Bs = list(As), list(Bs)
+        self.n = len(As)
+        self.dtype = _dtype_code(As[0], Bs[0]) if dtype is None else dtype
+        self.sorted = bool(sorted_output)
+        self.stream = stream
+        self.device = As[0].rpts.device
+        self._h = ctypes.c_void_p()
+        self._ca = (_Csr * self.n)(*[a._c() for a in self.As])
+        self._cb = (_Csr * self.n)(*[b._c() for b in self.Bs])
+        nbytes = _lib.spgemm_plan_scratch_bytes(self.n, self._ca)
+        self.plan_scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+        ws = ctypes.c_size_t(0)
+        flags = (SORTED if self.sorted else 0) | (VALIDATE if validate else 0)
+        st = _lib.spgemm_plan(ctypes.byref(self._h), self.n, self._ca, self._cb, self.dtype, flags,
+                              ctypes.c_void_p(self.plan_scratch.data_ptr()), _stream_handle(stream),
+                              ctypes.byref(ws))
+        _check(st, "spgemm_plan")
+        if timing:
+            _check(_lib.spgemm_plan_set_timing(self._h, 1), "spgemm_plan_set_timing")
+        self.workspace_bytes = int(ws.value)
+        self.workspace = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=self.device)
+        self.rpts_C: List[torch.Tensor] = []
+        self.nnz_C: List[int] = []
+        self.C: List[DeviceCSR] = []
+
+    def symbolic(self) -> List[int]:
+        self.rpts_C = [torch.empty(a.nrows + 1, dtype=torch.int64, device=self.device) for a in self.As]
+        arr = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in self.rpts_C])
+        nnz = (ctypes.c_int64 * self.n)()
+        st = _lib.spgemm_symbolic(self._h, ctypes.c_void_p(self.workspace.data_ptr()), arr, nnz)
+        _check(st, "spgemm_symbolic")
+        self.nnz_C = [int(x) for x in nnz]
+        return self.nnz_C
+
+    def allocate_output(self):
+        vt = torch.float64 if self.dtype == F64 else torch.int64
+        self.C = [DeviceCSR(a.nrows, b.ncols, rp, torch.empty(nz, dtype=torch.int32, device=self.device),
+                            torch.empty(nz, dtype=vt, device=self.device))
+                  for a, b, rp, nz in zip(self.As, self.Bs, self.rpts_C, self.nnz_C)]
+        return self.C
+
+    def numeric(self, As: Optional[Sequence[DeviceCSR]] = None, Bs: Optional[Sequence[DeviceCSR]] = None):
+        if As is not None:
+            self.As = list(As)
+            self._ca = (_Csr * self.n)(*[a._c() for a in self.As])
+        if Bs is not None:
+            self.Bs = list(Bs)
+            self._cb = (_Csr * self.n)(*[b._c() for b in self.Bs])
+        if not self.C:
+            self.allocate_output()
+        cc = (ctypes.c_void_p * self.n)(*[c.cols.data_ptr() for c in self.C])
+        cv = (ctypes.c_void_p * self.n)(*[c.vals.data_ptr() for c in self.C])
+        st = _lib.spgemm_numeric(self._h, self._ca, self._cb, cc, cv)
+        _check(st, "spgemm_numeric")
+        return self.C
+
+    def stats(self, i: int = 0) -> dict:
+        s = _Stats()
+        st = _lib.spgemm_plan_stats(self._h, i, ctypes.byref(s))
+        d = {f: int(getattr(s, f)) for f, _ in _Stats._fields_}
+        d["status"] = st
+        return d
+
+    def kernel_times(self) -> List[dict]:
+        buf = (_KTime * 64)()
+        n = _lib.spgemm_plan_kernel_times(self._h, buf, 64)
+        if n < 0:
+            _check(n, "spgemm_plan_kernel_times")
+        return [{"name": buf[i].name.decode(), "ms": buf[i].ms, "launches": int(buf[i].launches),
+                 "alg_bytes": buf[i].alg_bytes} for i in range(n)]
+
+    def close(self):
+        if self._h:
+            _lib.spgemm_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spgemm(A: DeviceCSR, B: DeviceCSR, sorted_output: bool = True, validate: bool = False,
+           stream=None) -> DeviceCSR:
+    """C = A @ B on the GPU (two-phase hash SpGEMM).  C has int64 row pointers."""
+    p = Plan([A], [B], sorted_output=sorted_output, validate=validate, stream=stream)
+    p.symbolic()
+    C = p.numeric()[0]
+    st = p.stats(0)
+    p.close()
+    if st["status"] != 0:
+        raise SpgemmError(st["status"], "spgemm (device check)")
+    return C
+
+
+def masked_sum_i64(C: DeviceCSR, M: DeviceCSR, stream=None) -> int:
+    """Sum of C_ij over the positions stored in M (int64, wrap-around), on the device."""
+    out = torch.empty(1, dtype=torch.int64, device=C.cols.device)
+    m = _Csr(M.nrows, M.ncols, M.nnz, M.rpts.data_ptr(), M.cols.data_ptr() if M.nnz else None, None)
+    st = _lib.spgemm_masked_sum_i64(C.nrows, C.ncols, ctypes.c_void_p(C.rpts.data_ptr()),
+                                    ctypes.c_void_p(C.cols.data_ptr() if C.nnz else None),
+                                    ctypes.c_void_p(C.vals.data_ptr() if C.nnz else None),
+                                    ctypes.byref(m), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    _check(st, "spgemm_masked_sum_i64")
+    return int(out.item())
+
+
+def triangle_count(A: DeviceCSR, L: DeviceCSR, U: DeviceCSR, stream=None) -> int:
+    """Triangles of the undirected graph A: sum(C o A) / 2 with C = L*U (int64, sorted rows)."""
+    C = spgemm(L, U, sorted_output=True, stream=stream)
+    s = masked_sum_i64(C, A, stream)
+    if s % 2:
+        raise SpgemmError(-10, "masked sum of L*U over symmetric A is odd")
+    return s // 2
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    n = min(dst.numel() * dst.element_size(), src.numel() * src.element_size()) // 16 * 16
+    _check(_lib.spgemm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n,
+                                   _stream_handle(stream)), "spgemm_stream_copy")

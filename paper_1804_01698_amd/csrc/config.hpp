@@ -1,0 +1,109 @@
+// Tunables and shared layouts of the gfx950 SpGEMM library (host and device).
+#pragma once
+#include <stdint.h>
+
+namespace spg {
+
+// ---- heavy rows: column windows --------------------------------------------
+// Rows whose output does not fit one LDS table are accumulated window by
+// window; a window is a run of whole 4096-column chunks holding at most
+// WIN_CAP output entries, accumulated in a WIN_TABLE-slot LDS hash table.
+constexpr int CHUNK_SHIFT = 12;
+constexpr int CHUNK_COLS = 1 << CHUNK_SHIFT;
+constexpr int WIN_TABLE = 11264;   // 132 KB of keys+values for 8-byte values
+constexpr int WIN_CAP = 8448;      // load factor <= 0.75
+constexpr int MAX_CHUNKS = 32768;  // heavy-row support: ncols <= 2^27
+
+// Symbolic bitmap for rows whose flop exceeds WIN_CAP: one bit per column of
+// C in LDS; wider matrices are swept in passes of BM_WORDS*32 columns.
+constexpr int BM_WORDS_SMALL = 2048;    //   8 KB:    65,536 columns
+constexpr int BM_WORDS_MID = 8192;      //  32 KB:   262,144 columns
+constexpr int BM_WORDS_LARGE = 36864;   // 144 KB: 1,179,648 columns
+
+// ---- bins -------------------------------------------------------------------
+// Symbolic bins by x = min(row flop, ncols): bin 0 = empty row, bins 1..9 LDS
+// hash tables of T >= 2x keys, bin 10 = bitmap.
+constexpr int NSB = 11;
+constexpr int SYM_BITMAP_BIN = 10;
+constexpr int SYM_G[NSB] = {0, 64, 64, 64, 128, 256, 256, 512, 1024, 1024, 1024};
+constexpr int SYM_T[NSB] = {0, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 0};
+constexpr int64_t SYM_XMAX[NSB] = {0, 32, 64, 128, 256, 512, 1024, 2048, 4096, WIN_CAP, INT64_MAX};
+
+// Numeric bins by exact nnz(c_i): bin 0 = empty row, bins 1..9 LDS hash
+// tables of keys+values, bin 10 = heavy (column windows).
+constexpr int NNB = 11;
+constexpr int NUM_HEAVY_BIN = 10;
+constexpr int NUM_G[NNB] = {0, 64, 64, 64, 128, 256, 256, 512, 1024, 1024, 1024};
+constexpr int NUM_T[NNB] = {0, 64, 128, 256, 512, 1024, 2048, 4096, 8192, WIN_TABLE, WIN_TABLE};
+constexpr int64_t NUM_XMAX[NNB] = {0, 32, 64, 128, 256, 512, 1024, 2048, 4096, WIN_CAP, INT64_MAX};
+
+__host__ __device__ inline int sym_bin(uint64_t flop, int64_t ncols) {
+    uint64_t x = flop < (uint64_t)ncols ? flop : (uint64_t)ncols;
+    if (x == 0) return 0;
+    for (int b = 1; b < SYM_BITMAP_BIN; ++b)
+        if (x <= (uint64_t)SYM_XMAX[b]) return b;
+    return SYM_BITMAP_BIN;
+}
+
+__host__ __device__ inline int num_bin(int64_t nnz) {
+    if (nnz <= 0) return 0;
+    for (int b = 1; b < NUM_HEAVY_BIN; ++b)
+        if (nnz <= NUM_XMAX[b]) return b;
+    return NUM_HEAVY_BIN;
+}
+
+// ---- device-side headers (counters the host reads back) ----------------------
+enum : int {
+    ERR_PROBE = 1,       // a hash probe sequence ran past the table size
+    ERR_COUNT = 2,       // numeric row count differs from the symbolic count
+    ERR_ITEMS = 4,       // window item list capacity exceeded
+    ERR_CSR = 8,         // malformed CSR (validate mode)
+    ERR_CHUNK = 16       // a heavy row has a chunk wider than a window
+};
+
+struct PlanHdr {
+    unsigned long long total_flop;
+    unsigned long long max_flop;
+    unsigned long long sym_rows[NSB];
+    unsigned long long sym_flop[NSB];
+    unsigned long long sym_nnza[NSB];
+    int err;
+    int pad_[7];
+};
+
+struct WsHdr {
+    unsigned long long nnz_c;
+    unsigned long long num_rows[NNB];
+    unsigned long long num_flop[NNB];
+    unsigned long long num_nnza[NNB];
+    unsigned long long num_nnzc[NNB];
+    unsigned int sym_cursor[NSB];
+    unsigned int num_cursor[NNB];
+    unsigned int n_heavy;
+    unsigned int n_items;
+    unsigned int n_long;
+    int err;
+    unsigned int probe_overflow;
+    int pad_[3];
+};
+
+// One column window of one heavy row.
+struct WinItem {
+    int32_t row;
+    int32_t ch_lo;      // first chunk (inclusive)
+    int32_t ch_hi;      // last chunk (exclusive)
+    int32_t count;      // output entries in the window (from the symbolic bitmap)
+    int64_t out_pos;    // absolute position in cols_C / vals_C
+};
+
+struct HeavyRow {
+    int32_t row;
+    int32_t slot;       // index of the row within the bitmap bin (chunk-count slot)
+};
+
+constexpr int PLAN_HDR_BYTES = 512;
+constexpr int WS_HDR_BYTES = 1024;
+static_assert(sizeof(PlanHdr) <= PLAN_HDR_BYTES, "plan header");
+static_assert(sizeof(WsHdr) <= WS_HDR_BYTES, "ws header");
+
+}  // namespace spg

@@ -1,0 +1,69 @@
+"""The C-ABI library loads on the host and exports every symbol the header declares;
+argument checks that return before any device work behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spgemm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spgemm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1804_01698_amd import binding
+    return binding._lib
+
+
+def test_header_declares_the_four_phase_calls():
+    names = _declared()
+    for n in ("spgemm_plan", "spgemm_symbolic", "spgemm_numeric", "spgemm_free"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_free_null(lib):
+    assert lib.spgemm_strerror(0) == b"ok"
+    assert b"shape" in lib.spgemm_strerror(-2)
+    assert lib.spgemm_free(None) == 0
+
+
+def test_host_side_argument_errors(lib):
+    from paper_1804_01698_amd import binding as b
+    A = b._Csr(4, 5, 0, 1, None, None)
+    B = b._Csr(6, 3, 0, 1, None, None)          # 5 != 6: shape mismatch
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t(0)
+    st = lib.spgemm_plan(ctypes.byref(h), 1, ctypes.byref(A), ctypes.byref(B), 0, 0,
+                         ctypes.c_void_p(1), None, ctypes.byref(ws))
+    assert st == -2 and not h.value
+    st = lib.spgemm_plan(None, 1, ctypes.byref(A), ctypes.byref(A), 0, 0, None, None, ctypes.byref(ws))
+    assert st == -1
+    B2 = b._Csr(5, 3, 0, 1, None, None)
+    st = lib.spgemm_plan(ctypes.byref(h), 1, ctypes.byref(A), ctypes.byref(B2), 7, 0,
+                         ctypes.c_void_p(1), None, ctypes.byref(ws))
+    assert st == -1                               # bad dtype
+    st = lib.spgemm_plan(ctypes.byref(h), 1, ctypes.byref(A), ctypes.byref(B2), 0, 1 << 9,
+                         ctypes.c_void_p(1), None, ctypes.byref(ws))
+    assert st == -1                               # unknown flag
+    assert lib.spgemm_symbolic(None, None, None, None) == -1
+    assert lib.spgemm_stream_copy(None, None, 15, None) == -1
+
+
+def test_plan_scratch_bytes(lib):
+    from paper_1804_01698_amd import binding as b
+    arr = (b._Csr * 2)(b._Csr(1000, 10, 0, 1, None, None), b._Csr(0, 10, 0, 1, None, None))
+    n = lib.spgemm_plan_scratch_bytes(2, arr)
+    assert n >= 1000 * 4 and n % 256 == 0
+    assert lib.spgemm_plan_scratch_bytes(0, arr) == 0

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle, element by
+element, on seeded inputs spanning every row bin, the column-window path of heavy
+rows, both output orders, both value types and the edge cases."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import (CSR, bfs_frontier, erdos_renyi_fixed_degree, from_dense, random_sparse, rmat,
+                   shuffle_within_rows, symmetric_rmat_graph, triangle_inputs, with_values)
+
+from _compare import assert_matches, assert_rows_match
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1804_01698_amd as sp
+    return sp
+
+
+def _dev(sp, a):
+    return sp.DeviceCSR.from_host(a, device="cuda")
+
+
+def _run(sp, A, B, sorted_output, validate=False):
+    import torch
+    dA, dB = _dev(sp, A), _dev(sp, B)
+    C = sp.spgemm(dA, dB, sorted_output=sorted_output, validate=validate)
+    torch.cuda.synchronize()
+    return C
+
+
+TINY = [
+    (1, 1, 1, 1.0, 0), (7, 5, 9, 0.3, 1), (33, 17, 29, 0.2, 2), (64, 64, 64, 0.1, 3),
+    (100, 80, 120, 0.3, 4), (300, 200, 500, 0.05, 5), (257, 1000, 3, 0.01, 6), (50, 50, 50, 0.9, 7),
+]
+
+
+@pytest.mark.parametrize("m,n,k,dens,seed", TINY)
+@pytest.mark.parametrize("sorted_output", [True, False])
+@pytest.mark.parametrize("vt", ["f64", "i64"])
+def test_random_small(sp, m, n, k, dens, seed, sorted_output, vt):
+    _note(f"case random_small m={m} n={n} k={k} dens={dens} seed={seed} sorted={sorted_output} {vt}")
+    A = random_sparse(m, n, dens, seed, values=vt, empty_rows=0.2, sorted_rows=False)
+    B = random_sparse(n, k, dens, seed + 50, values=vt, empty_rows=0.2, sorted_rows=False)
+    C = _run(sp, A, B, sorted_output)
+    assert_matches(C, oracle.spgemm(A, B, sorted_output=sorted_output), sorted_output)
+
+
+def test_empty_and_degenerate(sp):
+    _note("case empty_and_degenerate")
+    z = CSR(5, 4, np.zeros(6, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros(0))
+    b = random_sparse(4, 6, 0.5, 1)
+    for A, B in [(z, b), (random_sparse(3, 5, 0.5, 2), CSR(5, 4, np.zeros(6, dtype=np.int64),
+                                                            np.zeros(0, dtype=np.int32), np.zeros(0)))]:
+        C = _run(sp, A, B, True)
+        assert_matches(C, oracle.spgemm(A, B), True)
+    e = CSR(0, 3, np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros(0))
+    C = _run(sp, e, random_sparse(3, 3, 0.5, 3), True)
+    assert C.nnz == 0 and C.rpts.cpu().tolist() == [0]
+
+
+def test_structural_zero_and_wraparound(sp):
+    _note("case structural_zero_and_wraparound")
+    A = CSR(1, 2, np.array([0, 2]), np.array([0, 1]), np.array([1.0, -1.0]))
+    B = CSR(2, 1, np.array([0, 1, 2]), np.array([0, 0]), np.array([1.0, 1.0]))
+    C = _run(sp, A, B, True)
+    rp, cols, vals = C.to_host()
+    assert rp.tolist() == [0, 1] and cols.tolist() == [0] and vals.tolist() == [0.0]
+    A = CSR(1, 2, np.array([0, 2]), np.array([0, 1]), np.array([2**62, 2**62], dtype=np.int64))
+    B = CSR(2, 1, np.array([0, 1, 2]), np.array([0, 0]), np.array([2, 2], dtype=np.int64))
+    C = _run(sp, A, B, True)
+    assert C.to_host()[2].tolist() == [0]
+
+
+def test_er4096_sorted(sp):
+    """ER n=4096, 8 distinct uniform columns per row, A*A, sorted output."""
+    _note("case er4096_sorted")
+    A = erdos_renyi_fixed_degree(4096, 8, 1)
+    C = _run(sp, A, A, True)
+    assert_matches(C, oracle.spgemm(A, A, sorted_output=True), True)
+
+
+@pytest.mark.parametrize("scale", [10, 12, 14])
+@pytest.mark.parametrize("sorted_output", [True, False])
+def test_rmat_mid(sp, scale, sorted_output):
+    _note(f"case rmat_mid scale={scale} sorted={sorted_output}")
+    A = rmat(scale, 16, scale)
+    if not sorted_output:
+        A = shuffle_within_rows(A, 5)
+    C = _run(sp, A, A, sorted_output)
+    assert_matches(C, oracle.spgemm(A, A, sorted_output=sorted_output), sorted_output)
+
+
+@pytest.mark.parametrize("sorted_output", [True, False])
+def test_rmat16_full(sp, sorted_output):
+    """R-MAT scale 16 ef 16 A*A: every bin, bitmap symbolic and column windows."""
+    _note(f"case rmat16_full sorted={sorted_output}")
+    A = rmat(16, 16, 1)
+    if not sorted_output:
+        A = shuffle_within_rows(A, 3)
+    dA = _dev(sp, A)
+    p = sp.Plan([dA], [dA], sorted_output=sorted_output)
+    p.symbolic()
+    C = p.numeric()[0]
+    st = p.stats(0)
+    assert st["status"] == 0 and st["probe_overflow"] == 0
+    assert st["heavy_rows"] > 0 and st["windows"] > st["heavy_rows"]
+    assert st["flop"] == int(oracle.row_flop(A, A).sum())
+    assert_matches(C, oracle.spgemm(A, A, sorted_output=sorted_output), sorted_output)
+    p.close()
+
+
+def test_rmat_i64(sp):
+    _note("case rmat_i64")
+    A = with_values(rmat(13, 16, 4, values=""), 9, "i64", lo=-(2**40), hi=2**40)
+    A = shuffle_within_rows(A, 2)
+    for srt in (True, False):
+        C = _run(sp, A, A, srt)
+        assert_matches(C, oracle.spgemm(A, A, sorted_output=srt), srt)
+
+
+def test_wide_columns_multipass_bitmap(sp):
+    """B wider than one LDS bitmap (2,000,000 columns): the symbolic bitmap sweeps
+    in passes and the heavy row still splits into column windows."""
+    _note("case wide_columns_multipass_bitmap")
+    k = 2_000_000
+    B = erdos_renyi_fixed_degree(3000, 20, 7, ncols=k)
+    rng = np.random.default_rng(8)
+    rows = [np.sort(rng.choice(3000, size=s, replace=False)) for s in (1500, 30, 0, 700)]
+    rp = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum([r.size for r in rows], out=rp[1:])
+    A = with_values(CSR(len(rows), 3000, rp, np.concatenate(rows).astype(np.int32), None), 9, "f64")
+    for srt in (True, False):
+        C = _run(sp, A, B, srt)
+        assert_matches(C, oracle.spgemm(A, B, sorted_output=srt), srt)
+
+
+def test_rectangular_tall_skinny_bfs(sp):
+    """Multi-source BFS step: R-MAT scale 14 (int64 ones) times a frontier stack."""
+    _note("case bfs")
+    A = with_values(rmat(14, 16, 9, values=""), 0, "ones")
+    F = bfs_frontier(A.ncols, 512, 10)
+    for srt in (True, False):
+        C = _run(sp, A, F, srt)
+        ref = oracle.spgemm(A, F, sorted_output=srt)
+        assert_matches(C, ref, srt)
+        assert C.nnz == int(oracle.row_flop(A, F).sum())
+
+
+@pytest.mark.parametrize("degree_order", [False, True])
+def test_triangles(sp, degree_order):
+    _note(f"case triangles degree_order={degree_order}")
+    g = symmetric_rmat_graph(12, 16, 4)
+    A, L, U = triangle_inputs(g, degree_order=degree_order)
+    t = sp.triangle_count(_dev(sp, A), _dev(sp, L), _dev(sp, U))
+    assert t == oracle.triangle_count(A, L, U)
+    C = _run(sp, L, U, True)
+    assert_matches(C, oracle.spgemm(L, U, sorted_output=True), True)
+
+
+def test_triangles_closed_form(sp):
+    _note("case triangles_closed_form")
+    for n in (5, 100, 300):
+        d = np.ones((n, n), dtype=np.int64) - np.eye(n, dtype=np.int64)
+        A, L, U = triangle_inputs(from_dense(d))
+        assert sp.triangle_count(_dev(sp, A), _dev(sp, L), _dev(sp, U)) == n * (n - 1) * (n - 2) // 6
+    d = np.zeros((9, 9), dtype=np.int64)
+    d[:4, 4:] = 1
+    d[4:, :4] = 1
+    A, L, U = triangle_inputs(from_dense(d))
+    assert sp.triangle_count(_dev(sp, A), _dev(sp, L), _dev(sp, U)) == 0
+
+
+def test_repeat_runs_identical_pattern(sp):
+    _note("case determinism")
+    A = shuffle_within_rows(rmat(14, 16, 21), 1)
+    C1 = _run(sp, A, A, False)
+    C2 = _run(sp, A, A, False)
+    r1, c1, v1 = C1.to_host()
+    r2, c2, v2 = C2.to_host()
+    assert np.array_equal(r1, r2)
+    rows = np.repeat(np.arange(A.nrows), np.diff(r1))
+    o1, o2 = np.lexsort((c1, rows)), np.lexsort((c2, rows))
+    assert np.array_equal(c1[o1], c2[o2])
+    assert np.allclose(v1[o1], v2[o2], rtol=1e-12, atol=0)
+
+
+def test_numeric_reuse_with_new_values(sp):
+    """Plan and symbolic once, numeric twice with different values (same pattern)."""
+    _note("case numeric_reuse")
+    import torch
+    A1 = rmat(13, 16, 3)
+    A2 = with_values(A1, 77, "f64")
+    d1, d2 = _dev(sp, A1), _dev(sp, A2)
+    d2.rpts, d2.cols = d1.rpts, d1.cols
+    p = sp.Plan([d1], [d1], sorted_output=True)
+    p.symbolic()
+    C = p.numeric()[0]
+    torch.cuda.synchronize()
+    assert_matches(C, oracle.spgemm(A1, A1), True)
+    C = p.numeric([d2], [d2])[0]
+    torch.cuda.synchronize()
+    assert_matches(C, oracle.spgemm(A2, A2), True)
+    assert p.stats(0)["status"] == 0
+    p.close()
+
+
+def test_validate_rejects_bad_column(sp):
+    _note("case validate")
+    A = random_sparse(20, 10, 0.3, 1)
+    A.cols[3] = 10            # == ncols: out of range
+    B = random_sparse(10, 10, 0.3, 2)
+    with pytest.raises(sp.SpgemmError) as ei:
+        _run(sp, A, B, True, validate=True)
+    assert ei.value.status == -3
+
+
+def test_sampled_rows_api(sp):
+    """Row independence (P9) used for large products: rows of the full device
+    product equal the oracle computed on those rows alone."""
+    _note("case sampled_rows")
+    A = shuffle_within_rows(rmat(15, 16, 6), 4)
+    C = _run(sp, A, A, False)
+    f = oracle.row_flop(A, A)
+    rows = np.unique(np.concatenate([np.argsort(f)[-50:], np.random.default_rng(0).choice(A.nrows, 200)]))
+    ref = oracle.spgemm(A, A, sorted_output=False, rows=rows)
+    assert_rows_match(C, ref, rows, False)
