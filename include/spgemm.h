@@ -53,9 +53,11 @@ typedef enum {
 /* Flags for spgemm_plan. */
 enum {
     SPGEMM_SORTED = 1u << 0,   /* emit each row of C with ascending column ids     */
-    SPGEMM_VALIDATE = 1u << 1  /* check A and B structure on the device at plan time
+    SPGEMM_VALIDATE = 1u << 1, /* check A and B structure on the device at plan time
                                   (row pointers non-decreasing from 0 to nnz, column
                                   ids in range); failure gives SPGEMM_ERR_INVALID_CSR */
+    SPGEMM_TIMING = 1u << 2    /* record HIP events around every kernel launch from
+                                  the plan on (see spgemm_plan_kernel_times)        */
 };
 
 /* Status codes. */

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libspgemm.so")
 
 F64, I64 = 0, 1
-SORTED, VALIDATE = 1, 2
+SORTED, VALIDATE, TIMING = 1, 2, 4
 
 
 def lib_path() -> str:
@@ -159,13 +159,11 @@ class Plan:
         nbytes = _lib.spgemm_plan_scratch_bytes(self.n, self._ca)
         self.plan_scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
         ws = ctypes.c_size_t(0)
-        flags = (SORTED if self.sorted else 0) | (VALIDATE if validate else 0)
+        flags = (SORTED if self.sorted else 0) | (VALIDATE if validate else 0) | (TIMING if timing else 0)
         st = _lib.spgemm_plan(ctypes.byref(self._h), self.n, self._ca, self._cb, self.dtype, flags,
                               ctypes.c_void_p(self.plan_scratch.data_ptr()), _stream_handle(stream),
                               ctypes.byref(ws))
         _check(st, "spgemm_plan")
-        if timing:
-            _check(_lib.spgemm_plan_set_timing(self._h, 1), "spgemm_plan_set_timing")
         self.workspace_bytes = int(ws.value)
         self.workspace = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=self.device)
         self.rpts_C: List[torch.Tensor] = []

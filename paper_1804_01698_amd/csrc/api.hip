@@ -58,6 +58,7 @@ struct Prod {
     size_t ws_base = 0, ws_bytes = 0;
     size_t o_hdr = 0, o_perm_sym = 0, o_perm_num = 0, o_nnz = 0, o_bsum = 0;
     size_t o_chunk = 0, o_heavy = 0, o_items = 0, o_bc = 0, o_bv = 0, o_long = 0;
+    size_t o_whist = 0, o_long_id = 0, o_idx = 0, o_slot = 0, o_bperm = 0;
     // after symbolic
     char *ws = nullptr;
     WsHdr *wh = nullptr;
@@ -81,6 +82,7 @@ struct spgemm_plan_s {
     std::vector<Prod> prods;
     size_t ws_total = 0;
     bool timing = false;
+    int ncu = 256;
     std::vector<TimedLaunch> tl;
 };
 
@@ -152,7 +154,7 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     *out = nullptr;
     if (nprod <= 0 || !A || !B || !workspace_bytes) return SPGEMM_ERR_INVALID_ARG;
     if (dtype != SPGEMM_F64 && dtype != SPGEMM_I64) return SPGEMM_ERR_INVALID_ARG;
-    if (flags & ~(unsigned)(SPGEMM_SORTED | SPGEMM_VALIDATE)) return SPGEMM_ERR_INVALID_ARG;
+    if (flags & ~(unsigned)(SPGEMM_SORTED | SPGEMM_VALIDATE | SPGEMM_TIMING)) return SPGEMM_ERR_INVALID_ARG;
     for (int p = 0; p < nprod; ++p) {
         if (!csr_ok(A[p]) || !csr_ok(B[p])) return SPGEMM_ERR_INVALID_ARG;
         if (A[p].ncols != B[p].nrows) return SPGEMM_ERR_SHAPE;
@@ -165,6 +167,13 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     pl->dtype = (int)dtype;
     pl->flags = flags;
     pl->stream = stream;
+    pl->timing = (flags & SPGEMM_TIMING) != 0;
+    {
+        int devid = 0, ncu = 0;
+        if (hipGetDevice(&devid) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, devid) == hipSuccess && ncu > 0)
+            pl->ncu = ncu;
+    }
     pl->prods.resize(nprod);
     auto fail = [&](int st) { delete pl; return st; };
 
@@ -202,6 +211,7 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
         Prod &q = pl->prods[p];
         hipError_t e = timed(pl, "row_flop", 12.0 * q.A.nnz + 8.0 * q.m,
                              [&] { return launch_row_flop(q.A, q.B, q.flop, q.phdr, stream); });
+        if (e == hipSuccess) e = launch_count_long_b(q.B, q.phdr, stream);
         if (e != hipSuccess) return fail(hip_fail(e, "row_flop"));
     }
     for (int p = 0; p < nprod; ++p) {
@@ -235,16 +245,26 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
         q.o_perm_num = o; o += align_up(4 * m);
         q.o_nnz = o; o += align_up(4 * m);
         q.o_bsum = o; o += align_up(8 * (nb + 1));
+        q.o_slot = o; o += align_up(4 * m);
         if (q.nbm > 0) {
-            const unsigned long long cap = q.h.total_flop / (WIN_CAP - CHUNK_COLS) + (unsigned long long)q.nbm + 16;
+            // a closed window uses more than 2*RANK_BUDGET - (256 + 3*4096) half words
+            const unsigned long long per = 2ull * RANK_BUDGET - (2 * WORDS_PER_CHUNK + 3 * CHUNK_COLS);
+            const unsigned long long cap = 3ull * q.h.total_flop / per +
+                                           (unsigned long long)q.nbm *
+                                               (2ull * WORDS_PER_CHUNK * q.nchunks / per + 2) + 16;
             if (cap > 0xFFFFFFF0ull) return fail(SPGEMM_ERR_OVERFLOW);
             q.items_cap = (unsigned)cap;
+
             q.o_chunk = o; o += align_up(4 * (size_t)q.nbm * (size_t)q.nchunks);
             q.o_heavy = o; o += align_up(sizeof(HeavyRow) * (size_t)q.nbm);
             q.o_items = o; o += align_up(sizeof(WinItem) * (size_t)q.items_cap);
+            q.o_whist = o; o += align_up(sizeof(uint32_t) * 2 * (size_t)q.nchunks);
+            q.o_bperm = o; o += align_up(4 * (size_t)q.B.nnz);
             q.o_bc = o; o += align_up(4 * (size_t)q.B.nnz);
             q.o_bv = o; o += align_up(8 * (size_t)q.B.nnz);
             q.o_long = o; o += align_up(4 * (size_t)q.B.nrows);
+            q.o_long_id = o; o += align_up(4 * (size_t)q.B.nrows);
+            q.o_idx = o; o += align_up(4 * (size_t)q.h.n_long_b * (size_t)(q.nchunks + 1));
         }
         q.ws_bytes = o;
         ws += o;
@@ -274,8 +294,20 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
         BinOffsets off{};
         for (int b = 0; b < NSB; ++b) off.v[b] = q.sym_off[b];
         HIPCK(timed(pl, "sym_scatter", 8.0 * m,
-                    [&] { return launch_sym_scatter(m, q.flop, q.B.ncols, off, perm, nnz, q.wh, s); }),
+                    [&] {
+                        return launch_sym_scatter(m, q.flop, q.B.ncols, off, perm, nnz, q.at<int32_t>(q.o_slot),
+                                                  q.wh, s);
+                    }),
               "sym_scatter");
+        if (q.nbm > 0) {
+            HIPCK(timed(pl, "bucket_B", 8.0 * q.B.nrows + 16.0 * q.B.nnz,
+                        [&] {
+                            return launch_bucket(q.B, q.at<int32_t>(q.o_bc), q.at<int32_t>(q.o_bperm),
+                                                 q.at<int32_t>(q.o_long_id), q.at<int32_t>(q.o_long),
+                                                 q.at<int32_t>(q.o_idx), q.nchunks, q.wh, s);
+                        }),
+                  "bucket_B");
+        }
         // largest tables first: long-running blocks start early
         for (int b = NSB - 1; b >= 1; --b) {
             const unsigned nr = (unsigned)q.h.sym_rows[b];
@@ -284,9 +316,8 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
             if (b == SYM_BITMAP_BIN) {
                 HIPCK(timed(pl, "sym_bitmap", rows_bytes + 4.0 * nr * q.nchunks,
                             [&] {
-                                return launch_sym_bitmap(nr, perm, off.v[b], q.A, q.B, q.nchunks,
-                                                         q.at<uint32_t>(q.o_chunk), q.at<HeavyRow>(q.o_heavy),
-                                                         nnz, q.wh, s);
+                                return launch_sym_segments(nr, perm, off.v[b], q.A, q.B, q.nchunks,
+                                                           q.at<uint32_t>(q.o_chunk), nnz, s);
                             }),
                       "sym_bitmap");
             } else {
@@ -300,13 +331,18 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
         HIPCK(timed(pl, "scan", 16.0 * m + 8.0,
                     [&] { return launch_scan(nnz, m, q.at<long long>(q.o_bsum), q.rpts_C, q.wh, s); }),
               "scan");
-        HIPCK(timed(pl, "num_hist", 12.0 * m, [&] { return launch_num_hist(m, nnz, q.flop, q.A.rpts, q.wh, s); }),
+        HIPCK(timed(pl, "num_hist", 12.0 * m,
+                    [&] {
+                        return launch_num_hist(m, nnz, q.flop, q.A.rpts, q.at<int32_t>(q.o_slot),
+                                               q.at<HeavyRow>(q.o_heavy), q.wh, s);
+                    }),
               "num_hist");
         if (q.nbm > 0) {
             HIPCK(timed(pl, "windows", 8.0 * q.nbm * q.nchunks,
                         [&] {
                             return launch_windows((unsigned)q.nbm, q.at<HeavyRow>(q.o_heavy), q.nchunks,
-                                                  q.at<uint32_t>(q.o_chunk), q.rpts_C, q.at<WinItem>(q.o_items),
+                                                  q.at<uint32_t>(q.o_chunk), q.rpts_C, q.at<uint32_t>(q.o_whist),
+                                                  q.at<uint32_t>(q.o_whist) + q.nchunks, q.at<WinItem>(q.o_items),
                                                   q.items_cap, q.wh, s);
                         }),
                   "windows");
@@ -358,13 +394,12 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
         q.B.vals = B[p].vals;
         const unsigned nitems = q.hw.n_items;
         if (nitems > 0) {
-            HIPCK(hipMemsetAsync(&q.wh->n_long, 0, sizeof(unsigned), s), "hipMemsetAsync(n_long)");
-            HIPCK(timed(pl, "bucket_B", 8.0 * q.B.nrows + 24.0 * q.B.nnz,
+            HIPCK(timed(pl, "gather_B_vals", 20.0 * q.B.nnz,
                         [&] {
-                            return launch_bucket(pl->dtype, q.B, q.at<int32_t>(q.o_bc), q.at<void>(q.o_bv),
-                                                 q.at<int32_t>(q.o_long), q.nchunks, q.wh, s);
+                            return launch_gather_vals(pl->dtype, q.B.nnz, q.at<int32_t>(q.o_bperm), q.B.vals,
+                                                      q.at<void>(q.o_bv), s);
                         }),
-                  "bucket_B");
+                  "gather_B_vals");
         }
         const int32_t *perm = q.at<int32_t>(q.o_perm_num);
         for (int b = NUM_HEAVY_BIN - 1; b >= 1; --b) {
@@ -387,7 +422,8 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
                                  12.0 * q.hw.num_flop[hb] + 12.0 * q.hw.num_nnzc[hb];
             HIPCK(timed(pl, "num_window", bytes,
                         [&] {
-                            return launch_num_window(pl->dtype, sorted, nitems, q.at<WinItem>(q.o_items), q.A, q.B,
+                            return launch_num_window(pl->dtype, q.hw.n_items, q.at<WinItem>(q.o_items), q.A, q.B,
+                                                     q.at<int32_t>(q.o_long_id), q.at<int32_t>(q.o_idx), q.nchunks,
                                                      q.at<int32_t>(q.o_bc), q.at<void>(q.o_bv), cols_C[p],
                                                      vals_C[p], q.wh, s);
                         }),

@@ -12,9 +12,18 @@ constexpr int CHUNK_SHIFT = 12;
 constexpr int CHUNK_COLS = 1 << CHUNK_SHIFT;
 constexpr int WIN_TABLE = 11264;   // 132 KB of keys+values for 8-byte values
 constexpr int WIN_CAP = 8448;      // load factor <= 0.75
+// A column window of a heavy row holds, in LDS, one 64-bit word per 32
+// columns (occupancy bits + exclusive rank prefix), one value per output
+// entry and a 4-byte staging slot per entry: 128 words per chunk plus 1.5
+// words per entry must fit RANK_BUDGET words.
+constexpr int WORDS_PER_CHUNK = CHUNK_COLS / 32;
+constexpr int RANK_BUDGET = 17664;
 constexpr int MAX_CHUNKS = 32768;  // heavy-row support: ncols <= 2^27
+// B rows longer than SHORT_ROW get a chunk-offset index (slice of a window =
+// two loads); shorter rows are read whole and filtered by column.
+constexpr int SHORT_ROW = 16;
 
-// Symbolic bitmap for rows whose flop exceeds WIN_CAP: one bit per column of
+// Symbolic phase of rows whose flop exceeds WIN_CAP: one bit per column of
 // C in LDS; wider matrices are swept in passes of BM_WORDS*32 columns.
 constexpr int BM_WORDS_SMALL = 2048;    //   8 KB:    65,536 columns
 constexpr int BM_WORDS_MID = 8192;      //  32 KB:   262,144 columns
@@ -64,6 +73,7 @@ enum : int {
 struct PlanHdr {
     unsigned long long total_flop;
     unsigned long long max_flop;
+    unsigned long long n_long_b;   // rows of B longer than SHORT_ROW
     unsigned long long sym_rows[NSB];
     unsigned long long sym_flop[NSB];
     unsigned long long sym_nnza[NSB];
@@ -84,7 +94,8 @@ struct WsHdr {
     unsigned int n_long;
     int err;
     unsigned int probe_overflow;
-    int pad_[3];
+    unsigned int n_groups;
+    unsigned int pad2_[2];
 };
 
 // One column window of one heavy row.
@@ -100,6 +111,8 @@ struct HeavyRow {
     int32_t row;
     int32_t slot;       // index of the row within the bitmap bin (chunk-count slot)
 };
+
+
 
 constexpr int PLAN_HDR_BYTES = 512;
 constexpr int WS_HDR_BYTES = 1024;

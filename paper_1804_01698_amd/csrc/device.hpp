@@ -132,106 +132,188 @@ __device__ __forceinline__ void num_insert(int *keys, V *vals, uint32_t T, int k
     ovf = 1;
 }
 
+// ---- bucketed tables (vector probing) ----------------------------------------
+// The table is split into buckets of 4 consecutive slots read with one 16-byte
+// LDS load; a key is looked for in its whole bucket at once, a new key takes
+// the first empty slot of the bucket (slots fill from the front), and a full
+// bucket without the key sends the probe to the next bucket (linear probing
+// over buckets).  This is the chunked probing of the paper's HashVector
+// (Section 4.2.2) with a 4-slot chunk matched to one ds_read_b128.
+constexpr int BKT = 4;
+
+__device__ __forceinline__ int4 lds_load4(const int *p) {
+    return *reinterpret_cast<const int4 *>(p);
+}
+
+// Slot of key in the bucket (match or first empty), -1 if full without it;
+// empty_hit says the slot is empty (needs a CAS).
+__device__ __forceinline__ int bucket_pick(int4 k, int key, bool &empty_hit) {
+    empty_hit = false;
+    if (k.x == key) return 0;
+    if (k.y == key) return 1;
+    if (k.z == key) return 2;
+    if (k.w == key) return 3;
+    empty_hit = true;
+    if (k.x == -1) return 0;
+    if (k.y == -1) return 1;
+    if (k.z == -1) return 2;
+    if (k.w == -1) return 3;
+    empty_hit = false;
+    return -1;
+}
+
+// Insert key (and with NUM add x to its value); returns 1 if the key is new.
+// A probe that runs past every bucket without room sets ovf and gives up.
+template <bool NUM, typename V>
+__device__ __forceinline__ int bkt_insert(int *keys, V *vals, uint32_t T, int key, V x, int &ovf) {
+    const uint32_t NB = T / BKT;
+    uint32_t b = hash_slot(key, NB);
+    for (uint32_t it = 0; it < NB + T; ++it) {
+        __asm__ __volatile__("" ::: "memory");   // re-read the bucket every round
+        const int4 k = lds_load4(&keys[b * BKT]);
+        bool e;
+        const int j = bucket_pick(k, key, e);
+        if (j < 0) {
+            b = (b + 1 == NB) ? 0u : b + 1;
+            continue;
+        }
+        int added = 0;
+        if (e) {
+            const int old = atomicCAS(&keys[b * BKT + j], -1, key);
+            if (old != -1 && old != key) continue;    // lost the slot: look at this bucket again
+            added = old == -1;
+        }
+        if constexpr (NUM) lds_add(&vals[b * BKT + j], x);
+        return added;
+    }
+    ovf = 1;
+    return 0;
+}
+
 // ---- product enumeration ---------------------------------------------------
 // The products of one row of C are the pairs (a_ik, b_kj) for every stored
 // a_ik of the row and every b_kj of a slice of row k of B (the whole row, or
 // the part inside a column window).  A block of G threads takes the row's
-// A entries G at a time, lays their slices end to end (exclusive scan of the
-// slice lengths) and lets its waves pull batches of 64*U consecutive products
-// from a shared counter, so a few long B rows are spread over all waves.
-// Inside a batch, lane l of a 64-wide step owns product base+l; its segment
-// is found from a 64-bit mask of the segments starting in the step (one LDS
-// byte per start, read back with a ballot), not by a per-lane search.
+// A entries G at a time and lays their slices end to end (exclusive scan of
+// the slice lengths).  Wave w then owns the contiguous product range
+// [w*P/NW, (w+1)*P/NW), so a few long B rows are spread evenly over all
+// waves.  It walks its range in batches of 64*U products: the segments a
+// batch touches are found by galloping from the previous batch, and each
+// lane locates its U products' segments by U interleaved bisections over
+// that (usually tiny) range, so one batch costs a handful of LDS round trips
+// and one round of U independent global loads per lane.
 template <int G, bool NUM, typename V>
 struct SegLds {
     int lo[G];
     int off[G];
     V a[NUM ? G : 1];
     int wsum[G / WAVE + 1];
-    int next;
-    unsigned char mark[G / WAVE][WAVE];
 };
 
-template <int G, bool NUM, typename V>
-__device__ __forceinline__ void seg_init(SegLds<G, NUM, V> &sg) {
-    (&sg.mark[0][0])[threadIdx.x] = 0;
-}
-
-// slice(k, lo, hi): B-row k's products are B entries [lo, hi).
-// act(q[U], ok[U], a[U]): process up to U products per lane: B index q,
+// One chunk: this thread's entry has slice [lo, lo+len) and multiplier a.
+// act(q[U], ok[U], a[U]) processes up to U products per lane: B index q,
 // multiplier a (numeric phase), ok = valid.
-template <int G, int U, bool NUM, typename V, class SliceF, class ActF>
-__device__ __forceinline__ void enum_row(int a0, int a1, const int32_t *__restrict__ colsA,
-                                         const V *__restrict__ valsA, SegLds<G, NUM, V> &sg,
-                                         SliceF slice, ActF act) {
-    const int tid = threadIdx.x;
-    const int ln = tid & 63;
-    const int w = tid >> 6;
-    for (int cb = a0; cb < a1; cb += G) {
-        const int e = cb + tid;
-        int lo = 0, len = 0;
-        V a = V(0);
-        if (e < a1) {
-            int hi = 0;
-            slice(colsA[e], lo, hi);
-            len = hi - lo;
-            if constexpr (NUM) a = valsA[e];
-        }
-        int total, nseg;
-        const int pre_len = block_excl_scan<G, int>(len, total, sg.wsum);
-        const int pre_ne = block_excl_scan<G, int>(len > 0 ? 1 : 0, nseg, sg.wsum);
-        if (len > 0) {
-            sg.lo[pre_ne] = lo;
-            sg.off[pre_ne] = pre_len;
-            if constexpr (NUM) sg.a[pre_ne] = a;
-        }
-        if (tid == 0) sg.next = 0;
-        block_sync<G>();
-        for (;;) {
-            int pb = 0;
-            if (ln == 0) pb = atomicAdd(&sg.next, WAVE * U);
-            pb = __shfl(pb, 0);
-            if (pb >= total) break;
-            // last segment starting before pb (upper_bound(off, pb-1) - 1)
-            int lo_i = 0, hi_i = nseg;
-            while (lo_i < hi_i) {
-                const int mid = (lo_i + hi_i) >> 1;
-                if (sg.off[mid] <= pb - 1) lo_i = mid + 1; else hi_i = mid;
+template <int G, int U, bool NUM, typename V, bool SNUM, class ActF>
+__device__ __forceinline__ void enum_chunk(int lo, int len, V a, SegLds<G, SNUM, V> &sg, ActF act) {
+    static_assert(SNUM || !NUM, "numeric enumeration needs room for the multipliers");
+    constexpr int NW = G / WAVE;
+    const int ln = threadIdx.x & 63;
+    const int w = G == WAVE ? 0 : (int)(threadIdx.x >> 6);   // G == 64: one wave of a larger block
+    int total, nseg;
+    const int pre_len = block_excl_scan<G, int>(len, total, sg.wsum);
+    const int pre_ne = block_excl_scan<G, int>(len > 0 ? 1 : 0, nseg, sg.wsum);
+    if (len > 0) {
+        sg.lo[pre_ne] = lo;
+        sg.off[pre_ne] = pre_len;
+        if constexpr (NUM) sg.a[pre_ne] = a;
+    }
+    block_sync<G>();
+    const int P0 = (int)(((long long)w * total) / NW);
+    const int P1 = (int)(((long long)(w + 1) * total) / NW);
+    if (P0 < P1) {
+        int e = 0;
+        {
+            int hi = nseg - 1;
+            while (e < hi) {
+                const int mid = (e + hi + 1) >> 1;
+                if (sg.off[mid] <= P0) e = mid; else hi = mid - 1;
             }
-            int e_prev = lo_i - 1;
+        }
+        for (int pb = P0; pb < P1; pb += WAVE * U) {
+            const int last = min(pb + WAVE * U, P1) - 1;
+            int eh = e, step = 1;
+            while (eh + step < nseg && sg.off[eh + step] <= last) { eh += step; step <<= 1; }
+            int top = min(eh + step, nseg) - 1;
+            while (eh < top) {
+                const int mid = (eh + top + 1) >> 1;
+                if (sg.off[mid] <= last) eh = mid; else top = mid - 1;
+            }
             int q[U];
             bool ok[U];
             V av[U];
+            if (e == eh) {
+                // the whole batch lies in one segment: uniform base, no search
+                const int base = sg.lo[e] - sg.off[e] + pb + ln;
+                V a1 = V(0);
+                if constexpr (NUM) a1 = sg.a[e];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int base = pb + WAVE * u;
-                ok[u] = false;
-                q[u] = 0;
-                av[u] = V(0);
-                if (base < total) {
-                    const int cand = e_prev + 1 + ln;
-                    if (cand < nseg) {
-                        const int so = sg.off[cand];
-                        if (so < base + WAVE) sg.mark[w][so - base] = 1;
+                for (int u = 0; u < U; ++u) {
+                    ok[u] = pb + WAVE * u + ln <= last;
+                    q[u] = base + WAVE * u;
+                    av[u] = a1;
+                }
+            } else {
+                int ea[U], eb[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    ea[u] = e;
+                    eb[u] = eh;
+                }
+                const int r = eh - e;
+                const int steps = 32 - __clz(r);
+                for (int st = 0; st < steps; ++st) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (ea[u] < eb[u]) {
+                            const int mid = (ea[u] + eb[u] + 1) >> 1;
+                            if (sg.off[mid] <= pb + WAVE * u + ln) ea[u] = mid; else eb[u] = mid - 1;
+                        }
                     }
-                    wave_sync();
-                    const uint64_t M = __ballot(sg.mark[w][ln] != 0);
-                    sg.mark[w][ln] = 0;
-                    int eh = e_prev + __popcll(M & lanemask_le());
-                    eh = eh < 0 ? 0 : (eh >= nseg ? nseg - 1 : eh);
-                    const int p = base + ln;
-                    if (p < total) {
-                        ok[u] = true;
-                        q[u] = sg.lo[eh] + (p - sg.off[eh]);
-                        if constexpr (NUM) av[u] = sg.a[eh];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int p = pb + WAVE * u + ln;
+                    ok[u] = p <= last;
+                    q[u] = 0;
+                    av[u] = V(0);
+                    if (ok[u]) {
+                        q[u] = sg.lo[ea[u]] + (p - sg.off[ea[u]]);
+                        if constexpr (NUM) av[u] = sg.a[ea[u]];
                     }
-                    e_prev += __popcll(M);
-                    wave_sync();
                 }
             }
             act(q, ok, av);
+            e = eh;
         }
-        block_sync<G>();
+    }
+    block_sync<G>();
+}
+
+// All A entries [a0, a1) of a row, G at a time; slice(k, lo, hi) gives the
+// B entries [lo, hi) that a_ik multiplies.
+template <int G, int U, bool NUM, typename V, bool SNUM, class SliceF, class ActF>
+__device__ __forceinline__ void enum_row(int a0, int a1, const int32_t *__restrict__ colsA,
+                                         const V *__restrict__ valsA, SegLds<G, SNUM, V> &sg,
+                                         SliceF slice, ActF act) {
+    for (int cb = a0; cb < a1; cb += G) {
+        const int e = cb + (int)(threadIdx.x & (G - 1));
+        int lo = 0, hi = 0;
+        V a = V(0);
+        if (e < a1) {
+            slice(colsA[e], lo, hi);
+            if constexpr (NUM) a = valsA[e];
+        }
+        enum_chunk<G, U, NUM, V>(lo, hi - lo, a, sg, act);
     }
 }
 
@@ -306,8 +388,8 @@ __device__ __forceinline__ int compact_store(int *keys, V *vals, int *wsum, int6
     const int n = total < expected ? total : expected;
     if (total != expected && tid == 0) atomicOr(err, ERR_COUNT);
     for (int j = tid; j < n; j += G) {
-        colsC[out_pos + j] = keys[j];
-        valsC[out_pos + j] = vals[j];
+        __builtin_nontemporal_store(keys[j], &colsC[out_pos + j]);
+        __builtin_nontemporal_store(vals[j], &valsC[out_pos + j]);
     }
     return total;
 }

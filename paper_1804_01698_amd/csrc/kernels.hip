@@ -9,10 +9,12 @@
 //   k_scan_*         exclusive scan of row counts into int64 row pointers
 //   k_num_hist       rows grouped by exact nnz(c_i) for the numeric phase
 //   k_windows        column windows of the rows too large for one LDS table
-//   k_bucket_*       B rows reordered by 4096-column chunk (for windows)
+//   k_bucket_*       B rows reordered by 4096-column chunk, with a chunk index
+//   k_gather_vals    B values in that order (numeric phase)
 //   k_num_hash       numeric phase: LDS hash table of keys + values per row,
 //                    compacted (and sorted if asked) into C
-//   k_num_window     numeric phase of one column window of a heavy row
+//   k_num_window     numeric phase of a group of column windows of a heavy row:
+//                    occupancy bits, ranks, values added at their rank
 //   k_masked_sum     sum of C over the positions of a mask (triangle count)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,7 +25,14 @@
 
 namespace spg {
 
-constexpr int U_ENUM = 4;   // products per lane per batch (memory-level parallelism)
+// Products per lane per batch (memory-level parallelism), by kernel family.
+constexpr int U_SEG = 16;
+constexpr int U_RANK1 = 16;
+constexpr int U_RANK2 = 16;
+// hash bins: about the bin's largest row per thread, as a power of two <= 8
+__host__ __device__ constexpr int u_for(int G, int64_t xmax) {
+    return xmax <= G ? 1 : (xmax <= 2 * (int64_t)G ? 2 : (xmax <= 4 * (int64_t)G ? 4 : 8));
+}
 
 // ----------------------------------------------------------------------- validate
 
@@ -98,12 +107,22 @@ __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restri
     }
 }
 
+__global__ __launch_bounds__(256) void k_count_long_b(int n, const int32_t *__restrict__ rB, PlanHdr *hdr) {
+    __shared__ int ws[5];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int c = (i < n && rB[i + 1] - rB[i] > SHORT_ROW) ? 1 : 0;
+    int tot;
+    block_excl_scan<256, int>(c, tot, ws);
+    if (threadIdx.x == 0 && tot) atomicAdd(&hdr->n_long_b, (unsigned long long)tot);
+}
+
 // ----------------------------------------------------------------------- binning
 
 __global__ __launch_bounds__(256) void k_sym_scatter(int m, const uint32_t *__restrict__ flop,
                                                      int64_t ncolsB, BinOffsets off,
                                                      int32_t *__restrict__ perm,
-                                                     int32_t *__restrict__ nnz_row, WsHdr *wh) {
+                                                     int32_t *__restrict__ nnz_row,
+                                                     int32_t *__restrict__ slot_of, WsHdr *wh) {
     __shared__ unsigned int s_cnt[NSB], s_base[NSB];
     const int tid = threadIdx.x;
     if (tid < NSB) s_cnt[tid] = 0;
@@ -120,11 +139,18 @@ __global__ __launch_bounds__(256) void k_sym_scatter(int m, const uint32_t *__re
     if (tid < NSB && s_cnt[tid]) s_base[tid] = atomicAdd(&wh->sym_cursor[tid], s_cnt[tid]);
     __syncthreads();
     if (b > 0) perm[off.v[b] + s_base[b] + r] = i;
+    if (b == SYM_BITMAP_BIN) {
+        nnz_row[i] = 0;                       // summed over the row's work items
+        slot_of[i] = (int32_t)(s_base[b] + r);
+    }
 }
 
+// Rows grouped by nnz(c_i); rows above WIN_CAP are listed as heavy.
 __global__ __launch_bounds__(256) void k_num_hist(int m, const int32_t *__restrict__ nnz_row,
                                                   const uint32_t *__restrict__ flop,
-                                                  const int32_t *__restrict__ rA, WsHdr *wh) {
+                                                  const int32_t *__restrict__ rA,
+                                                  const int32_t *__restrict__ slot_of,
+                                                  HeavyRow *__restrict__ heavy, WsHdr *wh) {
     __shared__ unsigned long long s_rows[NNB], s_flop[NNB], s_nnza[NNB], s_nnzc[NNB];
     const int tid = threadIdx.x;
     if (tid < NNB) { s_rows[tid] = 0; s_flop[tid] = 0; s_nnza[tid] = 0; s_nnzc[tid] = 0; }
@@ -137,6 +163,7 @@ __global__ __launch_bounds__(256) void k_num_hist(int m, const int32_t *__restri
         atomicAdd(&s_flop[b], (unsigned long long)flop[i]);
         atomicAdd(&s_nnza[b], (unsigned long long)(rA[i + 1] - rA[i]));
         atomicAdd(&s_nnzc[b], (unsigned long long)nz);
+        if (b == NUM_HEAVY_BIN) heavy[atomicAdd(&wh->n_heavy, 1u)] = HeavyRow{i, slot_of[i]};
     }
     __syncthreads();
     if (tid < NNB && s_rows[tid]) {
@@ -170,31 +197,30 @@ __global__ __launch_bounds__(256) void k_num_scatter(int m, const int32_t *__res
 
 // ----------------------------------------------------------------------- symbolic
 
-template <int G, int T>
+template <int G, int T, int U>
 __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm, int64_t perm_off,
                                                 const int32_t *__restrict__ rA,
                                                 const int32_t *__restrict__ cA,
                                                 const int32_t *__restrict__ rB,
                                                 const int32_t *__restrict__ cB,
                                                 int32_t *__restrict__ nnz_row, WsHdr *wh) {
-    __shared__ int tab[T];
+    __shared__ __align__(16) int tab[T];
     __shared__ SegLds<G, false, double> sg;
     const int tid = threadIdx.x;
     const int row = perm[perm_off + blockIdx.x];
     for (int i = tid; i < T; i += G) tab[i] = -1;
-    seg_init(sg);
     __syncthreads();
     int cnt = 0, ovf = 0;
-    enum_row<G, U_ENUM, false, double>(
+    enum_row<G, U, false, double>(
         rA[row], rA[row + 1], cA, nullptr, sg,
         [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
-        [&](const int (&q)[U_ENUM], const bool (&ok)[U_ENUM], const double (&)[U_ENUM]) {
-            int col[U_ENUM];
+        [&](const int (&q)[U], const bool (&ok)[U], const double (&)[U]) {
+            int col[U];
 #pragma unroll
-            for (int u = 0; u < U_ENUM; ++u) col[u] = ok[u] ? cB[q[u]] : 0;
+            for (int u = 0; u < U; ++u) col[u] = ok[u] ? cB[q[u]] : 0;
 #pragma unroll
-            for (int u = 0; u < U_ENUM; ++u)
-                if (ok[u]) cnt += sym_insert(tab, T, col[u], ovf);
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf);
         });
     __syncthreads();
     int total;
@@ -206,8 +232,10 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
     }
 }
 
-// One bit per column of C (swept in passes of NWORDS*32 columns); the
-// per-chunk popcounts are kept for the window split of the numeric phase.
+// Symbolic phase of the bitmap-bin rows: one block per row, one LDS bit per
+// column of C (matrices wider than the bitmap are swept in passes of NWORDS*32
+// columns), then the popcount of every 4096-column chunk is kept for the
+// window split of the numeric phase.
 template <int NWORDS>
 __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__ perm, int64_t perm_off,
                                                      const int32_t *__restrict__ rA,
@@ -215,48 +243,46 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
                                                      const int32_t *__restrict__ rB,
                                                      const int32_t *__restrict__ cB, int64_t ncols,
                                                      int nchunks, uint32_t *__restrict__ chunk_cnt,
-                                                     HeavyRow *__restrict__ heavy,
-                                                     int32_t *__restrict__ nnz_row, WsHdr *wh) {
+                                                     int32_t *__restrict__ nnz_row) {
     constexpr int G = 1024;
     constexpr int NW = G / WAVE;
     constexpr int64_t WIN = (int64_t)NWORDS * 32;
-    static_assert(NWORDS % (CHUNK_COLS / 32) == 0, "bitmap pass must hold whole chunks");
+    static_assert(NWORDS % WORDS_PER_CHUNK == 0, "bitmap pass must hold whole chunks");
     __shared__ uint32_t bm[NWORDS];
     __shared__ SegLds<G, false, double> sg;
     __shared__ int s_total;
     const int tid = threadIdx.x, ln = tid & 63, w = tid >> 6;
     const int slot = blockIdx.x;
     const int row = perm[perm_off + slot];
-    seg_init(sg);
     if (tid == 0) s_total = 0;
     const int a0 = rA[row], a1 = rA[row + 1];
     const int npass = (int)((ncols + WIN - 1) / WIN);
     for (int pass = 0; pass < npass; ++pass) {
         const int64_t c0 = (int64_t)pass * WIN;
-        const int wcols = (int)(ncols - c0 < WIN ? ncols - c0 : WIN);
-        const int nw = (wcols + 31) >> 5;
+        const uint32_t wcols = (uint32_t)(ncols - c0 < WIN ? ncols - c0 : WIN);
+        const int nw = (int)((wcols + 31) >> 5);
         for (int i = tid; i < nw; i += G) bm[i] = 0;
         __syncthreads();
-        enum_row<G, U_ENUM, false, double>(
+        enum_row<G, U_SEG, false, double>(
             a0, a1, cA, nullptr, sg,
             [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
-            [&](const int (&q)[U_ENUM], const bool (&ok)[U_ENUM], const double (&)[U_ENUM]) {
-                int col[U_ENUM];
+            [&](const int (&q)[U_SEG], const bool (&ok)[U_SEG], const double (&)[U_SEG]) {
+                int col[U_SEG];
 #pragma unroll
-                for (int u = 0; u < U_ENUM; ++u) col[u] = ok[u] ? cB[q[u]] : 0;
+                for (int u = 0; u < U_SEG; ++u) col[u] = ok[u] ? cB[q[u]] : -1;
 #pragma unroll
-                for (int u = 0; u < U_ENUM; ++u) {
-                    const uint32_t c = (uint32_t)((int64_t)col[u] - c0);
-                    if (ok[u] && c < (uint32_t)wcols) atomicOr(&bm[c >> 5], 1u << (c & 31));
+                for (int u = 0; u < U_SEG; ++u) {
+                    const uint32_t off = (uint32_t)((int64_t)col[u] - c0);
+                    if (ok[u] && off < wcols) atomicOr(&bm[off >> 5], 1u << (off & 31));
                 }
             });
         __syncthreads();
-        const int nch = (wcols + CHUNK_COLS - 1) >> CHUNK_SHIFT;
+        const int nch = (int)((wcols + CHUNK_COLS - 1) >> CHUNK_SHIFT);
         const int chunk0 = (int)(c0 >> CHUNK_SHIFT);
         for (int c = w; c < nch; c += NW) {
             int cw = 0;
-            for (int j = ln; j < CHUNK_COLS / 32; j += WAVE) {
-                const int wi = c * (CHUNK_COLS / 32) + j;
+            for (int j = ln; j < WORDS_PER_CHUNK; j += WAVE) {
+                const int wi = c * WORDS_PER_CHUNK + j;
                 if (wi < nw) cw += __popc(bm[wi]);
             }
             cw = wave_sum_i32(cw);
@@ -267,13 +293,7 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        nnz_row[row] = s_total;
-        if (s_total > WIN_CAP) {
-            const unsigned h = atomicAdd(&wh->n_heavy, 1u);
-            heavy[h] = HeavyRow{row, slot};
-        }
-    }
+    if (tid == 0) nnz_row[row] = s_total;
 }
 
 // ----------------------------------------------------------------------- scan
@@ -334,118 +354,162 @@ __global__ __launch_bounds__(1024) void k_scan_down(const int32_t *__restrict__ 
 
 // ----------------------------------------------------------------------- windows
 
-__global__ __launch_bounds__(256) void k_windows(const HeavyRow *__restrict__ heavy, int nchunks,
-                                                 const uint32_t *__restrict__ chunk_cnt,
-                                                 const int64_t *__restrict__ rpts_C,
-                                                 WinItem *__restrict__ items, unsigned int cap,
-                                                 WsHdr *wh) {
+// Column windows of the heavy rows.  Greedy split of a row's chunks: a window
+// takes chunks while its LDS footprint fits RANK_BUDGET words (in half words:
+// 256 per chunk for its 128 bit/rank words, 3 per entry for the value word
+// and a half-word staging slot); empty chunks are not opened at a window
+// start.  The windows are laid out sorted by first chunk so that the blocks
+// running side by side read the same column slices of the shared B rows.
+template <class F>
+__device__ __forceinline__ void for_each_window(const uint32_t *__restrict__ cc, int nchunks, F f) {
+    int units = 0, cnt = 0, start = 0;
+    for (int c = 0; c < nchunks; ++c) {
+        const int x = (int)cc[c];
+        if (cnt == 0 && x == 0) { start = c + 1; continue; }
+        const int add = 2 * WORDS_PER_CHUNK + 3 * x;
+        if (units + add > 2 * RANK_BUDGET && cnt > 0) {
+            f(start, c, cnt);
+            start = c;
+            units = 0;
+            cnt = 0;
+        }
+        units += add;
+        cnt += x;
+    }
+    if (cnt > 0) f(start, nchunks, cnt);
+}
+
+__global__ __launch_bounds__(256) void k_win_count(const HeavyRow *__restrict__ heavy, int nchunks,
+                                                   const uint32_t *__restrict__ chunk_cnt,
+                                                   uint32_t *__restrict__ whist, WsHdr *wh) {
     const unsigned h = blockIdx.x * 256 + threadIdx.x;
     if (h >= wh->n_heavy) return;
     const HeavyRow hr = heavy[h];
     const uint32_t *cc = chunk_cnt + (size_t)hr.slot * nchunks;
-    int nwin = 0, cur = 0;
-    for (int c = 0; c < nchunks; ++c) {
-        const int x = (int)cc[c];
-        if (x > WIN_CAP) atomicOr(&wh->err, ERR_CHUNK);
-        if (cur + x > WIN_CAP && cur > 0) { ++nwin; cur = 0; }
-        cur += x;
+    unsigned n = 0;
+    for (int c = 0; c < nchunks; ++c)
+        if (cc[c] > (uint32_t)CHUNK_COLS) atomicOr(&wh->err, ERR_CHUNK);
+    for_each_window(cc, nchunks, [&](int lo, int, int) {
+        atomicAdd(&whist[lo], 1u);
+        ++n;
+    });
+    atomicAdd(&wh->n_items, n);
+}
+
+// exclusive scan of the per-chunk window counts (one block)
+__global__ __launch_bounds__(1024) void k_win_scan(uint32_t *__restrict__ whist, int nchunks,
+                                                   unsigned cap, WsHdr *wh) {
+    __shared__ int ws[17];
+    int carry = 0;
+    for (int c0 = 0; c0 < nchunks; c0 += 1024) {
+        const int c = c0 + (int)threadIdx.x;
+        const int v = c < nchunks ? (int)whist[c] : 0;
+        int tot;
+        const int ex = block_excl_scan<1024, int>(v, tot, ws);
+        if (c < nchunks) whist[c] = (uint32_t)(carry + ex);
+        carry += tot;
     }
-    if (cur > 0) ++nwin;
-    const unsigned base = atomicAdd(&wh->n_items, (unsigned)nwin);
-    if ((unsigned long long)base + nwin > cap) {
-        atomicOr(&wh->err, ERR_ITEMS);
-        return;
-    }
+    if (threadIdx.x == 0 && (unsigned)carry > cap) atomicOr(&wh->err, ERR_ITEMS);
+}
+
+__global__ __launch_bounds__(256) void k_win_emit(const HeavyRow *__restrict__ heavy, int nchunks,
+                                                  const uint32_t *__restrict__ chunk_cnt,
+                                                  const int64_t *__restrict__ rpts_C,
+                                                  const uint32_t *__restrict__ wpos, uint32_t *__restrict__ wcur,
+                                                  WinItem *__restrict__ items, unsigned cap, WsHdr *wh) {
+    const unsigned h = blockIdx.x * 256 + threadIdx.x;
+    if (h >= wh->n_heavy || (wh->err & ERR_ITEMS)) return;
+    const HeavyRow hr = heavy[h];
+    const uint32_t *cc = chunk_cnt + (size_t)hr.slot * nchunks;
     int64_t pos = rpts_C[hr.row];
-    int start = 0, k = 0;
-    cur = 0;
-    for (int c = 0; c < nchunks; ++c) {
-        const int x = (int)cc[c];
-        if (cur + x > WIN_CAP && cur > 0) {
-            items[base + k++] = WinItem{hr.row, start, c, cur, pos};
-            pos += cur;
-            start = c;
-            cur = 0;
-        }
-        cur += x;
-    }
-    if (cur > 0) items[base + k++] = WinItem{hr.row, start, nchunks, cur, pos};
+    for_each_window(cc, nchunks, [&](int lo, int hi, int cnt) {
+        const unsigned at = wpos[lo] + atomicAdd(&wcur[lo], 1u);
+        if (at < cap) items[at] = WinItem{hr.row, lo, hi, cnt, pos};
+        pos += cnt;
+    });
 }
 
 // ----------------------------------------------------------------------- bucket B by chunk
 
-// Rows of at most 64 entries: one wave sorts the row by column (rank count).
-template <typename V>
+// Rows of at most SHORT_ROW entries keep their order (windows read them whole
+// and filter by column); longer rows are listed for k_bucket_long.  bperm[p]
+// is the original position of the entry now at p (values follow in numeric).
 __global__ __launch_bounds__(256) void k_bucket_short(int n, const int32_t *__restrict__ rB,
                                                       const int32_t *__restrict__ cB,
-                                                      const V *__restrict__ vB,
-                                                      int32_t *__restrict__ bc, V *__restrict__ bv,
+                                                      int32_t *__restrict__ bc, int32_t *__restrict__ bperm,
+                                                      int32_t *__restrict__ long_id,
                                                       int32_t *__restrict__ long_list, WsHdr *wh) {
-    const int row = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    const int ln = threadIdx.x & 63;
+    const int row = blockIdx.x * 256 + (int)threadIdx.x;
     if (row >= n) return;
-    const int b0 = rB[row];
-    const int len = rB[row + 1] - b0;
-    if (len > WAVE) {
-        if (ln == 0) long_list[atomicAdd(&wh->n_long, 1u)] = row;
+    const int b0 = rB[row], b1 = rB[row + 1];
+    if (b1 - b0 > SHORT_ROW) {
+        const int li = (int)atomicAdd(&wh->n_long, 1u);
+        long_id[row] = li;
+        long_list[li] = row;
         return;
     }
-    const int col = ln < len ? cB[b0 + ln] : 0x7fffffff;
-    const V v = ln < len ? vB[b0 + ln] : V(0);
-    int rank = 0;
-    for (int j = 0; j < len; ++j) {
-        const int cj = __shfl(col, j);
-        rank += (cj < col) || (cj == col && j < ln);
-    }
-    if (ln < len) {
-        bc[b0 + rank] = col;
-        bv[b0 + rank] = v;
+    long_id[row] = -1;
+    for (int p = b0; p < b1; ++p) {
+        bc[p] = cB[p];
+        bperm[p] = p;
     }
 }
 
-// Longer rows: counting sort by chunk id with LDS counters (a block per row,
-// grid-stride over the list of long rows).
-template <typename V>
-__global__ __launch_bounds__(1024) void k_bucket_long(const int32_t *__restrict__ long_list,
-                                                      const WsHdr *wh, const int32_t *__restrict__ rB,
-                                                      const int32_t *__restrict__ cB,
-                                                      const V *__restrict__ vB,
-                                                      int32_t *__restrict__ bc, V *__restrict__ bv,
-                                                      int nchunks) {
-    __shared__ int cnt[MAX_CHUNKS];
-    __shared__ int ws[17];
+// Longer rows: counting sort by chunk id with LDS counters, and the chunk
+// offsets (relative to the row start) kept as the row's index:
+// idx[li*(nchunks+1) + c] = first position of chunk c, idx[..+nchunks] = len.
+template <int NCNT>
+__global__ __launch_bounds__(256) void k_bucket_long(const int32_t *__restrict__ long_list,
+                                                     const WsHdr *wh, const int32_t *__restrict__ rB,
+                                                     const int32_t *__restrict__ cB,
+                                                     int32_t *__restrict__ bc, int32_t *__restrict__ bperm,
+                                                     int32_t *__restrict__ idx, int nchunks) {
+    __shared__ int cnt[NCNT];
+    __shared__ int ws[5];
     const int tid = threadIdx.x;
     const unsigned nl = wh->n_long;
     for (unsigned li = blockIdx.x; li < nl; li += gridDim.x) {
         const int row = long_list[li];
         const int b0 = rB[row], b1 = rB[row + 1];
-        for (int c = tid; c < nchunks; c += 1024) cnt[c] = 0;
+        for (int c = tid; c < nchunks; c += 256) cnt[c] = 0;
         __syncthreads();
-        for (int p = b0 + tid; p < b1; p += 1024) atomicAdd(&cnt[cB[p] >> CHUNK_SHIFT], 1);
+        for (int p = b0 + tid; p < b1; p += 256) atomicAdd(&cnt[cB[p] >> CHUNK_SHIFT], 1);
         __syncthreads();
+        int32_t *ix = idx + (size_t)li * (nchunks + 1);
         int carry = 0;
-        for (int c0 = 0; c0 < nchunks; c0 += 1024) {
+        for (int c0 = 0; c0 < nchunks; c0 += 256) {
             const int c = c0 + tid;
             const int v = c < nchunks ? cnt[c] : 0;
             int tot;
-            const int ex = block_excl_scan<1024, int>(v, tot, ws);
-            if (c < nchunks) cnt[c] = carry + ex;
+            const int ex = block_excl_scan<256, int>(v, tot, ws);
+            if (c < nchunks) {
+                cnt[c] = carry + ex;
+                ix[c] = carry + ex;
+            }
             carry += tot;
         }
+        if (tid == 0) ix[nchunks] = b1 - b0;
         __syncthreads();
-        for (int p = b0 + tid; p < b1; p += 1024) {
+        for (int p = b0 + tid; p < b1; p += 256) {
             const int col = cB[p];
             const int pos = atomicAdd(&cnt[col >> CHUNK_SHIFT], 1);
             bc[b0 + pos] = col;
-            bv[b0 + pos] = vB[p];
+            bperm[b0 + pos] = p;
         }
         __syncthreads();
     }
 }
 
+template <typename V>
+__global__ __launch_bounds__(256) void k_gather_vals(int64_t n, const int32_t *__restrict__ bperm,
+                                                     const V *__restrict__ vB, V *__restrict__ bv) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += stride) bv[p] = vB[bperm[p]];
+}
+
 // ----------------------------------------------------------------------- numeric
 
-template <int G, int T, bool SORTED, typename V>
+template <int G, int T, int U, bool SORTED, typename V>
 __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm, int64_t perm_off,
                                                 const int32_t *__restrict__ rA,
                                                 const int32_t *__restrict__ cA,
@@ -456,30 +520,29 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
                                                 const int64_t *__restrict__ rpts_C,
                                                 int32_t *__restrict__ cC, V *__restrict__ vC,
                                                 WsHdr *wh) {
-    __shared__ int keys[T];
+    __shared__ __align__(16) int keys[T];
     __shared__ V vals[T];
     __shared__ SegLds<G, true, V> sg;
     const int tid = threadIdx.x;
     const int row = perm[perm_off + blockIdx.x];
     for (int i = tid; i < T; i += G) { keys[i] = -1; vals[i] = V(0); }
-    seg_init(sg);
     __syncthreads();
     int ovf = 0;
-    enum_row<G, U_ENUM, true, V>(
+    enum_row<G, U, true, V>(
         rA[row], rA[row + 1], cA, vA, sg,
         [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
-        [&](const int (&q)[U_ENUM], const bool (&ok)[U_ENUM], const V (&av)[U_ENUM]) {
-            int col[U_ENUM];
-            V bvv[U_ENUM];
+        [&](const int (&q)[U], const bool (&ok)[U], const V (&av)[U]) {
+            int col[U];
+            V x[U];
 #pragma unroll
-            for (int u = 0; u < U_ENUM; ++u) {
+            for (int u = 0; u < U; ++u) {
                 col[u] = 0;
-                bvv[u] = V(0);
-                if (ok[u]) { col[u] = cB[q[u]]; bvv[u] = vB[q[u]]; }
+                x[u] = V(0);
+                if (ok[u]) { col[u] = cB[q[u]]; x[u] = av[u] * vB[q[u]]; }
             }
 #pragma unroll
-            for (int u = 0; u < U_ENUM; ++u)
-                if (ok[u]) num_insert<V>(keys, vals, T, col[u], av[u] * bvv[u], ovf);
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf);
         });
     __syncthreads();
     if (ovf) {
@@ -491,63 +554,147 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
     compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
 }
 
-// first p in [lo, hi) whose column lies in chunk >= ch (B row bucketed by chunk)
-__device__ __forceinline__ int lower_chunk(const int32_t *__restrict__ bc, int lo, int hi, int ch) {
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((bc[mid] >> CHUNK_SHIFT) < ch) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-template <bool SORTED, typename V>
+// All column windows of one heavy row, in order, by one block.  A window's
+// output columns are marked first (one bit per column in LDS), their ranks
+// are the exclusive prefix of the bit counts, and the products are then
+// added straight into a dense array of values indexed by rank: no hashing,
+// no probing, and the window leaves in ascending column order.  The slice of
+// B row k inside the window is two loads from k's chunk index, or the whole
+// row (filtered by column) when the row is short.  The row's A entries (when
+// at most 1024) stay in registers across windows.
+template <typename V>
 __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__ items,
                                                      const int32_t *__restrict__ rA,
                                                      const int32_t *__restrict__ cA,
                                                      const V *__restrict__ vA,
                                                      const int32_t *__restrict__ rB,
+                                                     const int32_t *__restrict__ long_id,
+                                                     const int32_t *__restrict__ idx, int nchunks,
                                                      const int32_t *__restrict__ bc,
                                                      const V *__restrict__ bv,
                                                      int32_t *__restrict__ cC, V *__restrict__ vC,
                                                      WsHdr *wh) {
     constexpr int G = 1024;
-    constexpr int T = WIN_TABLE;
-    __shared__ int keys[T];
-    __shared__ V vals[T];
+    __shared__ __align__(16) unsigned long long buf[RANK_BUDGET];   // words, then values
     __shared__ SegLds<G, true, V> sg;
     const int tid = threadIdx.x;
     const WinItem it = items[blockIdx.x];
-    for (int i = tid; i < T; i += G) { keys[i] = -1; vals[i] = V(0); }
-    seg_init(sg);
-    __syncthreads();
-    int ovf = 0;
-    const int ch_lo = it.ch_lo, ch_hi = it.ch_hi;
-    enum_row<G, U_ENUM, true, V>(
-        rA[it.row], rA[it.row + 1], cA, vA, sg,
-        [&](int k, int &lo, int &hi) {
-            const int r0 = rB[k], r1 = rB[k + 1];
-            lo = lower_chunk(bc, r0, r1, ch_lo);
-            hi = lower_chunk(bc, lo, r1, ch_hi);
-        },
-        [&](const int (&q)[U_ENUM], const bool (&ok)[U_ENUM], const V (&av)[U_ENUM]) {
-            int col[U_ENUM];
-            V bvv[U_ENUM];
+    const int a0 = rA[it.row], a1 = rA[it.row + 1];
+    const bool resident = a1 - a0 <= G;
+    int r0 = 0, r1 = 0, li = -1;
+    V a = V(0);
+    if (resident && a0 + tid < a1) {
+        const int k = cA[a0 + tid];
+        a = vA[a0 + tid];
+        r0 = rB[k];
+        r1 = rB[k + 1];
+        li = long_id[k];
+    }
+    const int nch1 = nchunks + 1;
+    uint32_t *w32 = reinterpret_cast<uint32_t *>(buf);   // word w: bits w32[2w], rank prefix w32[2w+1]
+    bool bad = false;
+    {
+        const int ch_lo = it.ch_lo, ch_hi = it.ch_hi, count = it.count;
+        const int nwords = (ch_hi - ch_lo) * WORDS_PER_CHUNK;
+        const uint32_t span = (uint32_t)nwords * 32u;
+        const int c0 = ch_lo << CHUNK_SHIFT;
+        V *vals = reinterpret_cast<V *>(buf + nwords);
+        for (int i = tid; i < nwords; i += G) buf[i] = 0ull;
+        for (int i = tid; i < count; i += G) vals[i] = V(0);
+        __syncthreads();
+        auto slice = [&](int k, int &lo, int &hi) {
+            const int b0 = rB[k];
+            const int l = long_id[k];
+            if (l >= 0) {
+                const int32_t *ix = idx + (size_t)l * nch1;
+                lo = b0 + ix[ch_lo];
+                hi = b0 + ix[ch_hi];
+            } else {
+                lo = b0;
+                hi = rB[k + 1];
+            }
+        };
+        int lo = r0, hi = r1;
+        if (resident && li >= 0) {
+            const int32_t *ix = idx + (size_t)li * nch1;
+            lo = r0 + ix[ch_lo];
+            hi = r0 + ix[ch_hi];
+        }
+        // pass 1: occupancy bits
+        auto mark = [&](const int (&q)[U_RANK1], const bool (&ok)[U_RANK1], const V (&)[U_RANK1]) {
+            int col[U_RANK1];
 #pragma unroll
-            for (int u = 0; u < U_ENUM; ++u) {
-                col[u] = 0;
-                bvv[u] = V(0);
-                if (ok[u]) { col[u] = bc[q[u]]; bvv[u] = bv[q[u]]; }
+            for (int u = 0; u < U_RANK1; ++u) col[u] = ok[u] ? bc[q[u]] : c0 - 1;
+#pragma unroll
+            for (int u = 0; u < U_RANK1; ++u) {
+                const uint32_t off = (uint32_t)(col[u] - c0);
+                if (off < span) atomicOr(&w32[2 * (off >> 5)], 1u << (off & 31));
+            }
+        };
+        if (resident) enum_chunk<G, U_RANK1, false, V>(lo, hi - lo, V(0), sg, mark);
+        else enum_row<G, U_RANK1, false, V>(a0, a1, cA, nullptr, sg, slice, mark);
+        __syncthreads();
+        // ranks: exclusive prefix of the bit counts, per word
+        {
+            const int S = (nwords + G - 1) / G;
+            const int w0 = tid * S;
+            int c = 0;
+            for (int j = 0; j < S; ++j)
+                if (w0 + j < nwords) c += __popc(w32[2 * (w0 + j)]);
+            int total;
+            int pre = block_excl_scan<G, int>(c, total, sg.wsum);
+            for (int j = 0; j < S; ++j)
+                if (w0 + j < nwords) {
+                    w32[2 * (w0 + j) + 1] = (uint32_t)pre;
+                    pre += __popc(w32[2 * (w0 + j)]);
+                }
+            if (total != count) bad = true;
+        }
+        __syncthreads();
+        // pass 2: values added at their rank
+        auto add = [&](const int (&q)[U_RANK2], const bool (&ok)[U_RANK2], const V (&av)[U_RANK2]) {
+            int col[U_RANK2];
+            V x[U_RANK2];
+#pragma unroll
+            for (int u = 0; u < U_RANK2; ++u) {
+                col[u] = c0 - 1;
+                x[u] = V(0);
+                if (ok[u]) { col[u] = bc[q[u]]; x[u] = av[u] * bv[q[u]]; }
             }
 #pragma unroll
-            for (int u = 0; u < U_ENUM; ++u)
-                if (ok[u]) num_insert<V>(keys, vals, T, col[u], av[u] * bvv[u], ovf);
-        });
-    __syncthreads();
-    if (ovf) {
-        atomicAdd(&wh->probe_overflow, 1u);
-        atomicOr(&wh->err, ERR_PROBE);
+            for (int u = 0; u < U_RANK2; ++u) {
+                const uint32_t off = (uint32_t)(col[u] - c0);
+                if (off < span) {
+                    const uint2 e = reinterpret_cast<const uint2 *>(buf)[off >> 5];
+                    const uint32_t rank = e.y + __popc(e.x & ((1u << (off & 31)) - 1u));
+                    if (rank < (uint32_t)count) lds_add(&vals[rank], x[u]);
+                }
+            }
+        };
+        if (resident) enum_chunk<G, U_RANK2, true, V>(lo, hi - lo, a, sg, add);
+        else enum_row<G, U_RANK2, true, V>(a0, a1, cA, vA, sg, slice, add);
+        __syncthreads();
+        // columns staged in rank (= ascending column) order, then written out
+        // together with the values in consecutive runs
+        int32_t *stage = reinterpret_cast<int32_t *>(buf + nwords + count);
+        for (int w = tid; w < nwords; w += G) {
+            uint32_t bits = w32[2 * w];
+            uint32_t r = w32[2 * w + 1];
+            while (bits) {
+                const int j = __ffs(bits) - 1;
+                bits &= bits - 1;
+                if (r < (uint32_t)count) stage[r] = c0 + w * 32 + j;
+                ++r;
+            }
+        }
+        __syncthreads();
+        for (int r = tid; r < count; r += G) {
+            __builtin_nontemporal_store(stage[r], &cC[it.out_pos + r]);
+            __builtin_nontemporal_store(vals[r], &vC[it.out_pos + r]);
+        }
+        __syncthreads();
     }
-    compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, it.out_pos, it.count, cC, vC, &wh->err);
+    if (bad) atomicOr(&wh->err, ERR_COUNT);
 }
 
 // ----------------------------------------------------------------------- masked sum
@@ -641,16 +788,17 @@ hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, Pla
 }
 
 hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const BinOffsets &off,
-                              int32_t *perm, int32_t *nnz_row, WsHdr *wh, hipStream_t s) {
+                              int32_t *perm, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    k_sym_scatter<<<grid1(m, 256), 256, 0, s>>>(m, flop, ncolsB, off, perm, nnz_row, wh);
+    k_sym_scatter<<<grid1(m, 256), 256, 0, s>>>(m, flop, ncolsB, off, perm, nnz_row, slot_of, wh);
     return hipGetLastError();
 }
 
 template <int G, int T>
 static void sym_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
                        const CsrDev &B, int32_t *nnz_row, WsHdr *wh, hipStream_t s) {
-    k_sym_hash<G, T><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, nnz_row, wh);
+    constexpr int U = u_for(G, T / 2 + 1);
+    k_sym_hash<G, T, U><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, nnz_row, wh);
 }
 
 hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
@@ -671,27 +819,19 @@ hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t 
     return hipGetLastError();
 }
 
-int bitmap_words_for(int64_t ncols) {
-    const int64_t need = (ncols + 31) / 32;
-    if (need <= BM_WORDS_SMALL) return BM_WORDS_SMALL;
-    if (need <= BM_WORDS_MID) return BM_WORDS_MID;
-    return BM_WORDS_LARGE;
-}
-
-hipError_t launch_sym_bitmap(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                             const CsrDev &B, int nchunks, uint32_t *chunk_cnt, HeavyRow *heavy,
-                             int32_t *nnz_row, WsHdr *wh, hipStream_t s) {
-    if (nrows == 0) return hipSuccess;
-    const int words = bitmap_words_for(B.ncols);
-    if (words == BM_WORDS_SMALL)
-        k_sym_bitmap<BM_WORDS_SMALL><<<nrows, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols,
-                                                            nchunks, chunk_cnt, heavy, nnz_row, wh);
-    else if (words == BM_WORDS_MID)
-        k_sym_bitmap<BM_WORDS_MID><<<nrows, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols,
-                                                          nchunks, chunk_cnt, heavy, nnz_row, wh);
+hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
+                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, hipStream_t s) {
+    if (nbm == 0) return hipSuccess;
+    const int64_t need = (B.ncols + 31) / 32;
+    if (need <= BM_WORDS_SMALL)
+        k_sym_bitmap<BM_WORDS_SMALL><<<nbm, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks,
+                                                          chunk_cnt, nnz_row);
+    else if (need <= BM_WORDS_MID)
+        k_sym_bitmap<BM_WORDS_MID><<<nbm, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks,
+                                                        chunk_cnt, nnz_row);
     else
-        k_sym_bitmap<BM_WORDS_LARGE><<<nrows, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols,
-                                                            nchunks, chunk_cnt, heavy, nnz_row, wh);
+        k_sym_bitmap<BM_WORDS_LARGE><<<nbm, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks,
+                                                          chunk_cnt, nnz_row);
     return hipGetLastError();
 }
 
@@ -705,34 +845,49 @@ hipError_t launch_scan(const int32_t *nnz_row, int m, long long *bsum, int64_t *
 }
 
 hipError_t launch_num_hist(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
-                           WsHdr *wh, hipStream_t s) {
+                           const int32_t *slot_of, HeavyRow *heavy, WsHdr *wh, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    k_num_hist<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, flop, rA, wh);
+    k_num_hist<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, flop, rA, slot_of, heavy, wh);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_long_b(const CsrDev &B, PlanHdr *hdr, hipStream_t s) {
+    if (B.nrows == 0) return hipSuccess;
+    k_count_long_b<<<grid1(B.nrows, 256), 256, 0, s>>>((int)B.nrows, B.rpts, hdr);
     return hipGetLastError();
 }
 
 hipError_t launch_windows(unsigned nheavy_max, const HeavyRow *heavy, int nchunks, const uint32_t *chunk_cnt,
-                          const int64_t *rpts_C, WinItem *items, unsigned cap, WsHdr *wh, hipStream_t s) {
+                          const int64_t *rpts_C, uint32_t *whist, uint32_t *wcur, WinItem *items, unsigned cap,
+                          WsHdr *wh, hipStream_t s) {
     if (nheavy_max == 0) return hipSuccess;
-    k_windows<<<grid1(nheavy_max, 256), 256, 0, s>>>(heavy, nchunks, chunk_cnt, rpts_C, items, cap, wh);
+    hipError_t e = hipMemsetAsync(whist, 0, sizeof(uint32_t) * 2 * (size_t)nchunks, s);   // whist and wcur
+    if (e != hipSuccess) return e;
+    k_win_count<<<grid1(nheavy_max, 256), 256, 0, s>>>(heavy, nchunks, chunk_cnt, whist, wh);
+    k_win_scan<<<1, 1024, 0, s>>>(whist, nchunks, cap, wh);
+    k_win_emit<<<grid1(nheavy_max, 256), 256, 0, s>>>(heavy, nchunks, chunk_cnt, rpts_C, whist, wcur, items, cap, wh);
     return hipGetLastError();
 }
 
-template <typename V>
-static hipError_t bucket_t(const CsrDev &B, int32_t *bc, void *bv, int32_t *long_list, int nchunks,
-                           WsHdr *wh, hipStream_t s) {
+hipError_t launch_bucket(const CsrDev &B, int32_t *bc, int32_t *bperm, int32_t *long_id, int32_t *long_list,
+                         int32_t *idx, int nchunks, WsHdr *wh, hipStream_t s) {
     if (B.nrows == 0) return hipSuccess;
-    k_bucket_short<V><<<grid1(B.nrows, 4), 256, 0, s>>>((int)B.nrows, B.rpts, B.cols, (const V *)B.vals, bc,
-                                                         (V *)bv, long_list, wh);
-    k_bucket_long<V><<<1024, 1024, 0, s>>>(long_list, wh, B.rpts, B.cols, (const V *)B.vals, bc, (V *)bv,
-                                            nchunks);
+    k_bucket_short<<<grid1(B.nrows, 256), 256, 0, s>>>((int)B.nrows, B.rpts, B.cols, bc, bperm, long_id, long_list,
+                                                        wh);
+    if (nchunks <= 1024)
+        k_bucket_long<1024><<<4096, 256, 0, s>>>(long_list, wh, B.rpts, B.cols, bc, bperm, idx, nchunks);
+    else
+        k_bucket_long<MAX_CHUNKS><<<1024, 256, 0, s>>>(long_list, wh, B.rpts, B.cols, bc, bperm, idx, nchunks);
     return hipGetLastError();
 }
 
-hipError_t launch_bucket(int dtype, const CsrDev &B, int32_t *bc, void *bv, int32_t *long_list, int nchunks,
-                         WsHdr *wh, hipStream_t s) {
-    if (dtype == 0) return bucket_t<double>(B, bc, bv, long_list, nchunks, wh, s);
-    return bucket_t<unsigned long long>(B, bc, bv, long_list, nchunks, wh, s);
+hipError_t launch_gather_vals(int dtype, int64_t n, const int32_t *bperm, const void *vB, void *bv, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>(grid1(n, 256), 256 * 32);
+    if (dtype == 0) k_gather_vals<double><<<g, 256, 0, s>>>(n, bperm, (const double *)vB, (double *)bv);
+    else k_gather_vals<unsigned long long><<<g, 256, 0, s>>>(n, bperm, (const unsigned long long *)vB,
+                                                             (unsigned long long *)bv);
+    return hipGetLastError();
 }
 
 hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &off, int32_t *perm, WsHdr *wh,
@@ -745,7 +900,8 @@ hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &o
 template <int G, int T, bool SORTED, typename V>
 static void num_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
                        const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s) {
-    k_num_hash<G, T, SORTED, V><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, (const V *)A.vals, B.rpts, B.cols,
+    constexpr int U = u_for(G, T / 2 + 1) < 4 ? u_for(G, T / 2 + 1) : 4;
+    k_num_hash<G, T, U, SORTED, V><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, (const V *)A.vals, B.rpts, B.cols,
                                                      (const V *)B.vals, rpts_C, cC, (V *)vC, wh);
 }
 
@@ -779,24 +935,18 @@ hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const
                   : num_bin_t<false, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, s);
 }
 
-template <bool SORTED, typename V>
-static void num_window_l(unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
-                         const int32_t *bc, const void *bv, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s) {
-    k_num_window<SORTED, V><<<nitems, 1024, 0, s>>>(items, A.rpts, A.cols, (const V *)A.vals, B.rpts, bc,
-                                                    (const V *)bv, cC, (V *)vC, wh);
-}
-
-hipError_t launch_num_window(int dtype, bool sorted, unsigned nitems, const WinItem *items, const CsrDev &A,
-                             const CsrDev &B, const int32_t *bc, const void *bv, int32_t *cC, void *vC,
-                             WsHdr *wh, hipStream_t s) {
+// Windows leave in ascending column order, so sorted and unsorted output share it.
+hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
+                             const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
+                             const void *bv, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    if (dtype == 0) {
-        if (sorted) num_window_l<true, double>(nitems, items, A, B, bc, bv, cC, vC, wh, s);
-        else num_window_l<false, double>(nitems, items, A, B, bc, bv, cC, vC, wh, s);
-    } else {
-        if (sorted) num_window_l<true, unsigned long long>(nitems, items, A, B, bc, bv, cC, vC, wh, s);
-        else num_window_l<false, unsigned long long>(nitems, items, A, B, bc, bv, cC, vC, wh, s);
-    }
+    if (dtype == 0)
+        k_num_window<double><<<nitems, 1024, 0, s>>>(items, A.rpts, A.cols, (const double *)A.vals, B.rpts, long_id,
+                                                     idx, nchunks, bc, (const double *)bv, cC, (double *)vC, wh);
+    else
+        k_num_window<unsigned long long><<<nitems, 1024, 0, s>>>(
+            items, A.rpts, A.cols, (const unsigned long long *)A.vals, B.rpts, long_id, idx, nchunks, bc,
+            (const unsigned long long *)bv, cC, (unsigned long long *)vC, wh);
     return hipGetLastError();
 }
 

@@ -20,33 +20,34 @@ struct BinOffsets {
     int64_t v[NSB > NNB ? NSB : NNB];
 };
 
-int bitmap_words_for(int64_t ncols);
 
 hipError_t launch_validate(const CsrDev &a, int *err, hipStream_t s);
 hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, PlanHdr *hdr, hipStream_t s);
 hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const BinOffsets &off,
-                              int32_t *perm, int32_t *nnz_row, WsHdr *wh, hipStream_t s);
+                              int32_t *perm, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh, hipStream_t s);
 hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
                           const CsrDev &B, int32_t *nnz_row, WsHdr *wh, hipStream_t s);
-hipError_t launch_sym_bitmap(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                             const CsrDev &B, int nchunks, uint32_t *chunk_cnt, HeavyRow *heavy,
-                             int32_t *nnz_row, WsHdr *wh, hipStream_t s);
+hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
+                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, hipStream_t s);
 hipError_t launch_scan(const int32_t *nnz_row, int m, long long *bsum, int64_t *rpts_C, WsHdr *wh,
                        hipStream_t s);
 hipError_t launch_num_hist(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
-                           WsHdr *wh, hipStream_t s);
+                           const int32_t *slot_of, HeavyRow *heavy, WsHdr *wh, hipStream_t s);
+hipError_t launch_count_long_b(const CsrDev &B, PlanHdr *hdr, hipStream_t s);
 hipError_t launch_windows(unsigned nheavy_max, const HeavyRow *heavy, int nchunks, const uint32_t *chunk_cnt,
-                          const int64_t *rpts_C, WinItem *items, unsigned cap, WsHdr *wh, hipStream_t s);
-hipError_t launch_bucket(int dtype, const CsrDev &B, int32_t *bc, void *bv, int32_t *long_list, int nchunks,
-                         WsHdr *wh, hipStream_t s);
+                          const int64_t *rpts_C, uint32_t *whist, uint32_t *wcur, WinItem *items, unsigned cap,
+                          WsHdr *wh, hipStream_t s);
+hipError_t launch_bucket(const CsrDev &B, int32_t *bc, int32_t *bperm, int32_t *long_id, int32_t *long_list,
+                         int32_t *idx, int nchunks, WsHdr *wh, hipStream_t s);
+hipError_t launch_gather_vals(int dtype, int64_t n, const int32_t *bperm, const void *vB, void *bv, hipStream_t s);
 hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &off, int32_t *perm, WsHdr *wh,
                               hipStream_t s);
 hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
                           const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
                           WsHdr *wh, hipStream_t s);
-hipError_t launch_num_window(int dtype, bool sorted, unsigned nitems, const WinItem *items, const CsrDev &A,
-                             const CsrDev &B, const int32_t *bc, const void *bv, int32_t *cC, void *vC,
-                             WsHdr *wh, hipStream_t s);
+hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
+                             const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
+                             const void *bv, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s);
 hipError_t launch_masked_sum(int64_t m, int64_t ncols, const int64_t *rC, const int32_t *cC, const int64_t *vC,
                              const CsrDev &M, int64_t *out, hipStream_t s);
 hipError_t launch_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t s);
