@@ -189,6 +189,67 @@ int spgemm_masked_sum_i64(int64_t nrows, int64_t ncols, const int64_t *rpts_C, c
  */
 int spgemm_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------- batches
+ *
+ * Many small independent products through one fixed sequence of launches per
+ * batch, with no host synchronisation inside spgemm_batch_run (the sequence
+ * can be captured in a HIP graph and replayed).  Every row of every product is
+ * binned by its key bound min(row flop, ncols) (the row flop of Fig. 4) and
+ * accumulated in one pass into an LDS hash table of the size the single
+ * product path uses for that bound (Section 4.2.1); its entries are staged in
+ * a bound-sized slot of a caller-provided arena and then compacted into CSR
+ * inside the arena: the one-phase scheme of Section 2 (allocate an upper
+ * bound, then compact).  Rows whose key bound exceeds 8448 are outside the
+ * batched range: their product gets status SPGEMM_ERR_UNSUPPORTED (use the
+ * plan path for it).  Operands must be valid CSR (see spgemm_csr); the batch
+ * path does not validate them.  The total row count of a batch must be below
+ * 2^31 - 1.  Calls that overlap on one scratch or arena race.
+ */
+typedef struct {
+    int64_t flop;       /* multiplications of the product                           */
+    int64_t nnz;        /* nnz(C)                                                  */
+    int64_t rpts_off;   /* byte offset in the arena of C's int64 row pointers       */
+    int64_t cols_off;   /* byte offset in the arena of C's int32 column ids         */
+    int64_t vals_off;   /* byte offset in the arena of C's values                   */
+    int32_t status;     /* SPGEMM_OK, SPGEMM_ERR_UNSUPPORTED or SPGEMM_ERR_INTERNAL */
+    int32_t pad;
+} spgemm_batch_result;
+
+/* Device scratch bytes for a batch whose left operands are A[0..nprod-1]
+ * (0 for an invalid batch). */
+size_t spgemm_batch_scratch_bytes(int nprod, const spgemm_csr *A);
+
+/* Upload the batch description (device pointers of A[p], B[p], per-product
+ * flags: SPGEMM_SORTED or 0) into scratch.  Host arrays may be reused on
+ * return (the call waits for its copy).  Errors: SPGEMM_ERR_INVALID_ARG
+ * (counts, pointers, flags), SPGEMM_ERR_SHAPE (A[p].ncols != B[p].nrows). */
+int spgemm_batch_prepare(int nprod, const spgemm_csr *A, const spgemm_csr *B, const unsigned *flags,
+                         void *scratch, hipStream_t stream);
+
+/* Analyse a prepared batch: the row flop of every row (Fig. 4), its bin and
+ * its staging slot, kept in scratch for every later run; per product, into
+ * host arrays of nprod: flop[p] (multiplications), bound[p] (sum over the
+ * product's batched rows of min(row flop, ncols): an upper bound of
+ * nnz(C[p])) and, if max_key is not NULL, max_key[p] (largest
+ * min(row flop, ncols) of the product).  Synchronises stream (used for
+ * admission and arena sizing).  Operand values are not read. */
+int spgemm_batch_analyse(int nprod, const spgemm_csr *A, void *scratch, int64_t *flop, int64_t *bound,
+                         int64_t *max_key, hipStream_t stream);
+
+/* Arena bytes for a batch with the given per-product bounds (host array):
+ * 24 bytes per bounded entry plus 8 per row pointer, 256-byte aligned parts. */
+size_t spgemm_batch_arena_bytes(int nprod, const spgemm_csr *A, const int64_t *bound);
+
+/* Run a prepared batch: every product C[p] = A[p]*B[p] lands in the arena;
+ * results (device array of nprod) says where.  bound is the host array that
+ * spgemm_batch_analyse returned (it fixes the arena layout; operand values may
+ * change between runs, their structure may not: rows whose bound no longer
+ * fits the arena come out empty with status SPGEMM_ERR_INTERNAL).  Launches kernels
+ * only (no memset, no copy, no synchronisation): capturable in a HIP graph.
+ * SPGEMM_ERR_WORKSPACE if arena_bytes is below spgemm_batch_arena_bytes. */
+int spgemm_batch_run(int nprod, const spgemm_csr *A, spgemm_dtype dtype, const int64_t *bound, void *scratch,
+                     void *arena, size_t arena_bytes, spgemm_batch_result *results, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

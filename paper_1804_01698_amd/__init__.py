@@ -6,6 +6,8 @@ stream.  The binding raises ``ImportError`` when the library has not been built:
 there is no CPU fallback.
 """
 from .binding import (
+    Batch,
+    BATCH_XMAX,
     DeviceCSR,
     Plan,
     SpgemmError,
@@ -21,6 +23,6 @@ from .binding import (
 )
 
 __all__ = [
-    "DeviceCSR", "Plan", "SpgemmError", "F64", "I64", "SORTED", "VALIDATE", "lib_path",
+    "Batch", "BATCH_XMAX", "DeviceCSR", "Plan", "SpgemmError", "F64", "I64", "SORTED", "VALIDATE", "lib_path",
     "masked_sum_i64", "spgemm", "stream_copy", "triangle_count",
 ]

@@ -73,6 +73,18 @@ def _load():
     lib.spgemm_masked_sum_i64.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, ctypes.POINTER(_Csr), P, P]
     lib.spgemm_stream_copy.restype = ctypes.c_int
     lib.spgemm_stream_copy.argtypes = [P, P, ctypes.c_size_t, P]
+    lib.spgemm_batch_scratch_bytes.restype = ctypes.c_size_t
+    lib.spgemm_batch_scratch_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr)]
+    lib.spgemm_batch_prepare.restype = ctypes.c_int
+    lib.spgemm_batch_prepare.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr), ctypes.POINTER(_Csr),
+                                         ctypes.POINTER(ctypes.c_uint), P, P]
+    lib.spgemm_batch_analyse.restype = ctypes.c_int
+    lib.spgemm_batch_analyse.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr), P, i64p, i64p, i64p, P]
+    lib.spgemm_batch_arena_bytes.restype = ctypes.c_size_t
+    lib.spgemm_batch_arena_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr), i64p]
+    lib.spgemm_batch_run.restype = ctypes.c_int
+    lib.spgemm_batch_run.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr), ctypes.c_int, i64p, P, P,
+                                     ctypes.c_size_t, P, P]
     return lib
 
 
@@ -226,6 +238,77 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+BATCH_RESULT_BYTES = 48   # spgemm_batch_result: 5 x int64 + 2 x int32
+BATCH_XMAX = 8448          # rows above this key bound are outside the batched range
+
+
+class Batch:
+    """Many small products C[p] = A[p] @ B[p] through one fixed sequence of
+    launches (spgemm_batch_*).  ``run()`` enqueues kernels only (capturable in a
+    HIP graph); ``outputs()`` reads the per-product results back and returns
+    views into the arena."""
+
+    def __init__(self, As: Sequence[DeviceCSR], Bs: Sequence[DeviceCSR], sorted_flags=True,
+                 dtype: Optional[int] = None, stream=None):
+        if len(As) != len(Bs) or not As:
+            raise ValueError("need equal, non-empty lists of operands")
+        self.As, self.Bs = list(As), list(Bs)
+        self.n = len(As)
+        self.dtype = _dtype_code(As[0], Bs[0]) if dtype is None else dtype
+        self.device = As[0].rpts.device
+        self.stream = stream
+        if isinstance(sorted_flags, bool):
+            sorted_flags = [sorted_flags] * self.n
+        self.sorted = [bool(x) for x in sorted_flags]
+        self._ca = (_Csr * self.n)(*[a._c() for a in self.As])
+        self._cb = (_Csr * self.n)(*[b._c() for b in self.Bs])
+        nb = _lib.spgemm_batch_scratch_bytes(self.n, self._ca)
+        self.scratch = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
+        flags = (ctypes.c_uint * self.n)(*[SORTED if x else 0 for x in self.sorted])
+        _check(_lib.spgemm_batch_prepare(self.n, self._ca, self._cb, flags,
+                                         ctypes.c_void_p(self.scratch.data_ptr()), _stream_handle(stream)),
+               "spgemm_batch_prepare")
+        self._flop = (ctypes.c_int64 * self.n)()
+        self._bound = (ctypes.c_int64 * self.n)()
+        self._maxk = (ctypes.c_int64 * self.n)()
+        _check(_lib.spgemm_batch_analyse(self.n, self._ca, ctypes.c_void_p(self.scratch.data_ptr()), self._flop,
+                                      self._bound, self._maxk, _stream_handle(stream)), "spgemm_batch_analyse")
+        self.flop = [int(x) for x in self._flop]
+        self.bound = [int(x) for x in self._bound]
+        self.max_key = [int(x) for x in self._maxk]
+        self.arena_bytes = int(_lib.spgemm_batch_arena_bytes(self.n, self._ca, self._bound))
+        self.arena = torch.empty(max(self.arena_bytes, 1), dtype=torch.uint8, device=self.device)
+        self.results = torch.zeros(self.n * BATCH_RESULT_BYTES, dtype=torch.uint8, device=self.device)
+
+    def run(self, stream=None):
+        st = _lib.spgemm_batch_run(self.n, self._ca, self.dtype, self._bound,
+                                   ctypes.c_void_p(self.scratch.data_ptr()), ctypes.c_void_p(self.arena.data_ptr()),
+                                   self.arena_bytes, ctypes.c_void_p(self.results.data_ptr()),
+                                   _stream_handle(stream if stream is not None else self.stream))
+        _check(st, "spgemm_batch_run")
+
+    def outputs(self) -> List[Optional[DeviceCSR]]:
+        """Per-product results as DeviceCSR views into the arena (None where the
+        product is outside the batched range)."""
+        raw = self.results.cpu().numpy()
+        ints = raw.view(np.int64).reshape(self.n, BATCH_RESULT_BYTES // 8)
+        status = raw.view(np.int32).reshape(self.n, BATCH_RESULT_BYTES // 4)[:, 10]
+        vt = torch.float64 if self.dtype == F64 else torch.int64
+        out: List[Optional[DeviceCSR]] = []
+        self.status = [int(x) for x in status]
+        for p in range(self.n):
+            if status[p] != 0:
+                out.append(None)
+                continue
+            nnz, ro, co, vo = (int(ints[p, 1]), int(ints[p, 2]), int(ints[p, 3]), int(ints[p, 4]))
+            m = self.As[p].nrows
+            rp = self.arena[ro:ro + 8 * (m + 1)].view(torch.int64)
+            cl = self.arena[co:co + 4 * nnz].view(torch.int32)
+            vl = self.arena[vo:vo + 8 * nnz].view(vt)
+            out.append(DeviceCSR(m, self.Bs[p].ncols, rp, cl, vl))
+        return out
 
 
 def spgemm(A: DeviceCSR, B: DeviceCSR, sorted_output: bool = True, validate: bool = False,

@@ -54,6 +54,12 @@ __host__ __device__ inline int sym_bin(uint64_t flop, int64_t ncols) {
     return SYM_BITMAP_BIN;
 }
 
+// Products per lane per enumeration batch of a hash bin: about the bin's
+// largest row per thread, as a power of two <= 8.
+__host__ __device__ constexpr int u_for(int G, int64_t xmax) {
+    return xmax <= G ? 1 : (xmax <= 2 * (int64_t)G ? 2 : (xmax <= 4 * (int64_t)G ? 4 : 8));
+}
+
 __host__ __device__ inline int num_bin(int64_t nnz) {
     if (nnz <= 0) return 0;
     for (int b = 1; b < NUM_HEAVY_BIN; ++b)

@@ -29,10 +29,6 @@ namespace spg {
 constexpr int U_SEG = 16;
 constexpr int U_RANK1 = 16;
 constexpr int U_RANK2 = 16;
-// hash bins: about the bin's largest row per thread, as a power of two <= 8
-__host__ __device__ constexpr int u_for(int G, int64_t xmax) {
-    return xmax <= G ? 1 : (xmax <= 2 * (int64_t)G ? 2 : (xmax <= 4 * (int64_t)G ? 4 : 8));
-}
 
 // ----------------------------------------------------------------------- validate
 
