@@ -8,6 +8,9 @@ there is no CPU fallback.
 from .binding import (
     Batch,
     BATCH_XMAX,
+    batch_arena_bytes,
+    batch_scratch_bytes,
+    plan_scratch_bytes,
     DeviceCSR,
     Plan,
     SpgemmError,
@@ -23,6 +26,6 @@ from .binding import (
 )
 
 __all__ = [
-    "Batch", "BATCH_XMAX", "DeviceCSR", "Plan", "SpgemmError", "F64", "I64", "SORTED", "VALIDATE", "lib_path",
+    "Batch", "BATCH_XMAX", "batch_arena_bytes", "batch_scratch_bytes", "plan_scratch_bytes", "DeviceCSR", "Plan", "SpgemmError", "F64", "I64", "SORTED", "VALIDATE", "lib_path",
     "masked_sum_i64", "spgemm", "stream_copy", "triangle_count",
 ]

@@ -156,7 +156,8 @@ class Plan:
     the library itself allocates no device memory."""
 
     def __init__(self, As: Sequence[DeviceCSR], Bs: Sequence[DeviceCSR], sorted_output: bool = True,
-                 dtype: Optional[int] = None, validate: bool = False, stream=None, timing: bool = False):
+                 dtype: Optional[int] = None, validate: bool = False, stream=None, timing: bool = False,
+                 defer_workspace: bool = False):
         if len(As) != len(Bs) or not As:
             raise ValueError("need equal, non-empty lists of operands")
         self.As, self.Bs = list(As), list(Bs)
@@ -177,12 +178,23 @@ class Plan:
                               ctypes.byref(ws))
         _check(st, "spgemm_plan")
         self.workspace_bytes = int(ws.value)
-        self.workspace = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=self.device)
+        self.workspace = None
+        if not defer_workspace:
+            self.allocate_workspace()
         self.rpts_C: List[torch.Tensor] = []
         self.nnz_C: List[int] = []
         self.C: List[DeviceCSR] = []
 
+    def allocate_workspace(self):
+        if self.workspace is None:
+            self.workspace = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=self.device)
+
+    def output_bytes(self) -> int:
+        """Device bytes of C (after symbolic): int32 columns and 8-byte values."""
+        return 12 * sum(self.nnz_C)
+
     def symbolic(self) -> List[int]:
+        self.allocate_workspace()
         self.rpts_C = [torch.empty(a.nrows + 1, dtype=torch.int64, device=self.device) for a in self.As]
         arr = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in self.rpts_C])
         nnz = (ctypes.c_int64 * self.n)()
@@ -240,18 +252,39 @@ class Plan:
             pass
 
 
+def plan_scratch_bytes(As: Sequence[DeviceCSR]) -> int:
+    """Device bytes Plan allocates before spgemm_plan (host-side query)."""
+    ca = (_Csr * len(As))(*[a._c() for a in As])
+    return int(_lib.spgemm_plan_scratch_bytes(len(As), ca))
+
+
+def batch_scratch_bytes(As: Sequence[DeviceCSR]) -> int:
+    """Device scratch bytes of a batch with these left operands."""
+    ca = (_Csr * len(As))(*[a._c() for a in As])
+    return int(_lib.spgemm_batch_scratch_bytes(len(As), ca))
+
+
+def batch_arena_bytes(As: Sequence[DeviceCSR], bounds: Sequence[int]) -> int:
+    """Arena bytes of a batch with these left operands and per-product bounds."""
+    ca = (_Csr * len(As))(*[a._c() for a in As])
+    b = (ctypes.c_int64 * len(As))(*bounds)
+    return int(_lib.spgemm_batch_arena_bytes(len(As), ca, b))
+
+
 BATCH_RESULT_BYTES = 48   # spgemm_batch_result: 5 x int64 + 2 x int32
 BATCH_XMAX = 8448          # rows above this key bound are outside the batched range
 
 
 class Batch:
     """Many small products C[p] = A[p] @ B[p] through one fixed sequence of
-    launches (spgemm_batch_*).  ``run()`` enqueues kernels only (capturable in a
-    HIP graph); ``outputs()`` reads the per-product results back and returns
-    views into the arena."""
+    launches (spgemm_batch_*).  Construction uploads the batch and analyses it
+    (row flop, bins, staging offsets; synchronises the stream) and, unless
+    ``allocate=False``, allocates the arena (``arena_bytes``).  ``run()``
+    enqueues kernels only (capturable in a HIP graph); ``outputs()`` reads the
+    per-product results back and returns views into the arena."""
 
     def __init__(self, As: Sequence[DeviceCSR], Bs: Sequence[DeviceCSR], sorted_flags=True,
-                 dtype: Optional[int] = None, stream=None):
+                 dtype: Optional[int] = None, stream=None, allocate: bool = True):
         if len(As) != len(Bs) or not As:
             raise ValueError("need equal, non-empty lists of operands")
         self.As, self.Bs = list(As), list(Bs)
@@ -265,7 +298,9 @@ class Batch:
         self._ca = (_Csr * self.n)(*[a._c() for a in self.As])
         self._cb = (_Csr * self.n)(*[b._c() for b in self.Bs])
         nb = _lib.spgemm_batch_scratch_bytes(self.n, self._ca)
-        self.scratch = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
+        if nb == 0:
+            raise SpgemmError(-1, "spgemm_batch_scratch_bytes: invalid batch")
+        self.scratch = torch.empty(nb, dtype=torch.uint8, device=self.device)
         flags = (ctypes.c_uint * self.n)(*[SORTED if x else 0 for x in self.sorted])
         _check(_lib.spgemm_batch_prepare(self.n, self._ca, self._cb, flags,
                                          ctypes.c_void_p(self.scratch.data_ptr()), _stream_handle(stream)),
@@ -274,15 +309,30 @@ class Batch:
         self._bound = (ctypes.c_int64 * self.n)()
         self._maxk = (ctypes.c_int64 * self.n)()
         _check(_lib.spgemm_batch_analyse(self.n, self._ca, ctypes.c_void_p(self.scratch.data_ptr()), self._flop,
-                                      self._bound, self._maxk, _stream_handle(stream)), "spgemm_batch_analyse")
+                                         self._bound, self._maxk, _stream_handle(stream)), "spgemm_batch_analyse")
         self.flop = [int(x) for x in self._flop]
         self.bound = [int(x) for x in self._bound]
         self.max_key = [int(x) for x in self._maxk]
         self.arena_bytes = int(_lib.spgemm_batch_arena_bytes(self.n, self._ca, self._bound))
-        self.arena = torch.empty(max(self.arena_bytes, 1), dtype=torch.uint8, device=self.device)
-        self.results = torch.zeros(self.n * BATCH_RESULT_BYTES, dtype=torch.uint8, device=self.device)
+        self.arena = None
+        self.results = None
+        self.status: List[int] = []
+        if allocate:
+            self.allocate()
+
+    @property
+    def supported(self) -> List[bool]:
+        """Products whose every row lies inside the batched range."""
+        return [k <= BATCH_XMAX for k in self.max_key]
+
+    def allocate(self):
+        if self.arena is None:
+            self.arena = torch.empty(max(self.arena_bytes, 1), dtype=torch.uint8, device=self.device)
+            self.results = torch.zeros(self.n * BATCH_RESULT_BYTES, dtype=torch.uint8, device=self.device)
 
     def run(self, stream=None):
+        if self.arena is None:
+            raise SpgemmError(-6, "Batch.run: arena not allocated")
         st = _lib.spgemm_batch_run(self.n, self._ca, self.dtype, self._bound,
                                    ctypes.c_void_p(self.scratch.data_ptr()), ctypes.c_void_p(self.arena.data_ptr()),
                                    self.arena_bytes, ctypes.c_void_p(self.results.data_ptr()),
@@ -291,7 +341,7 @@ class Batch:
 
     def outputs(self) -> List[Optional[DeviceCSR]]:
         """Per-product results as DeviceCSR views into the arena (None where the
-        product is outside the batched range)."""
+        product is outside the batched range or failed; see ``status``)."""
         raw = self.results.cpu().numpy()
         ints = raw.view(np.int64).reshape(self.n, BATCH_RESULT_BYTES // 8)
         status = raw.view(np.int32).reshape(self.n, BATCH_RESULT_BYTES // 4)[:, 10]
