@@ -37,6 +37,8 @@ WORKLOADS = {
                        "count=sum(C o A)/2", sorted=True),
     "bfs18": dict(desc="C=A*F, A R-MAT scale 18 ef 16 int64 ones, F n x 512 one nonzero per column, "
                        "unsorted output", sorted=False),
+    "serve": dict(desc="served stream: Poisson arrivals, n log-uniform [256, 131072], nnz/row U{2..32}, "
+                       "ER/R-MAT 50/50, sorted/unsorted 50/50, A and B independent, FP64", sorted=None),
 }
 
 
@@ -82,8 +84,11 @@ def main():
     ap.add_argument("--unsorted", dest="sorted_flag", action="store_false")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-flop-budget", type=float, default=3e9,
-                    help="multiplications in the oracle's row sample")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target oracle time of the CPU baseline's row sample")
+    ap.add_argument("--requests", type=int, default=4000, help="serve: requests in the stream")
+    ap.add_argument("--small-requests", type=int, default=256, help="serve: requests of the small stratum")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: admission budget")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel HIP events")
     args = ap.parse_args()
 
@@ -91,6 +96,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the row-parallel "
               "multi-GPU split is a design note, not part of this build.", file=sys.stderr)
         sys.exit(2)
+
+    host_serve = None
+    if args.workload == "serve":
+        # operands are generated on a host process pool before anything touches the GPU
+        host_serve = _generate_serve(args)
 
     import torch
     import paper_1804_01698_amd as sp
@@ -100,6 +110,8 @@ def main():
         sys.exit(3)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "serve":
+        return bench_serve(args, sp, dev, *host_serve)
 
     t_gen = time.perf_counter()
     inp = make_inputs(args.workload, args.seed, args.sorted_flag)
@@ -182,8 +194,9 @@ def main():
         name, kms, nl, bytes_per_launch = kernels[0]
         avg_launch_ms = kms / max(nl, 1)
         achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+        traffic = counted_traffic(name, args.workload)
         roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "avg_launch_ms": round(avg_launch_ms, 4), "alg_bytes_per_launch": bytes_per_launch}
     nnz_a, nnz_b, m = inp["A"].nnz, inp["B"].nnz, inp["A"].nrows
     path_bytes = 16.0 * flop + 12.0 * nnz_c + 44.0 * nnz_a + 40.0 * m
@@ -214,27 +227,221 @@ def main():
         out["triangles"] = int(extra) // 2
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inp, args.cpu_flop_budget, srt, args.seed)
+        out["cpu_baseline"] = cpu_baseline(inp, args.cpu_seconds, srt, args.seed)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(inp, budget, srt, seed):
-    """The oracle, as it is, on a seeded random sample of rows of the same product."""
+KERNEL_SOURCES = ("paper_1804_01698_amd/csrc/kernels.hip", "paper_1804_01698_amd/csrc/device.hpp",
+                  "paper_1804_01698_amd/csrc/config.hpp")
+
+
+def counted_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of ``kernel`` on ``workload`` from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if fields.get("kernel") != kernel or fields.get("source_sha256") != h.hexdigest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(inp, seconds, srt, seed):
+    """The oracle, as it is, on a seeded random sample of rows of the same
+    product, streamed in row blocks of at most 1e9 multiplications whose results
+    are dropped (the whole product's C does not fit host memory).  A first
+    block measures the rate; the sample is then sized to about ``seconds``."""
     import oracle
     A, B = inp["A"], inp["B"]
-    f = oracle.row_flop(A, B)
+    f = oracle.row_flop(A, B).astype(np.int64)
     order = np.random.default_rng(seed + 99).permutation(A.nrows)
     csum = np.cumsum(f[order])
-    k = int(np.searchsorted(csum, budget)) + 1
-    rows = np.sort(order[:min(k, A.nrows)])
-    sflop = int(f[rows].sum())
     threads = oracle.max_threads()
-    t0 = time.perf_counter()
-    oracle.spgemm(A, B, sorted_output=srt, rows=rows)
-    dt = time.perf_counter() - t0
-    return {"value": round(2.0 * sflop / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rows.size} random rows of the same product ({sflop} multiplications, "
-                      f"{sflop / max(int(f.sum()), 1):.3%} of the flop), {dt:.1f} s"}
+
+    def run(lo_flop, hi_flop):
+        lo = int(np.searchsorted(csum, lo_flop, side="right"))
+        hi = min(int(np.searchsorted(csum, hi_flop, side="right")) + 1, A.nrows)
+        rows_all = order[lo:hi]
+        t = 0.0
+        done = 0
+        i = 0
+        while i < rows_all.size:
+            j = i
+            acc = 0
+            while j < rows_all.size and (acc == 0 or acc + f[rows_all[j]] <= 1e9):
+                acc += f[rows_all[j]]
+                j += 1
+            rows = np.sort(rows_all[i:j])
+            t0 = time.perf_counter()
+            C = oracle.spgemm(A, B, sorted_output=srt, rows=rows)
+            t += time.perf_counter() - t0
+            del C
+            done += acc
+            i = j
+        return hi - lo, done, t
+
+    n1, fl1, t1 = run(0, 5e8)
+    rate = fl1 / max(t1, 1e-9)
+    target = min(float(csum[-1]), fl1 + rate * max(seconds - t1, 0.0))
+    n2, fl2, t2 = run(fl1, target) if target > fl1 else (0, 0, 0.0)
+    nrows, flop, dt = n1 + n2, fl1 + fl2, t1 + t2
+    passes = 1
+    if nrows >= A.nrows:
+        # the whole product took less than the target: repeat it
+        total = int(csum[-1])
+        while dt < seconds:
+            t0 = time.perf_counter()
+            C = oracle.spgemm(A, B, sorted_output=srt)
+            dt += time.perf_counter() - t0
+            del C
+            flop += total
+            passes += 1
+    what = (f"the whole product x {passes}" if nrows >= A.nrows else
+            f"{nrows} random rows of the same product ({flop / max(int(csum[-1]), 1):.3%} of the flop)")
+    return {"value": round(float(2.0 * flop / dt / 1e9), 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what}, {flop} multiplications in row blocks of <= 1e9, {dt:.1f} s"}
+
+
+def _gen_request(r):
+    from synth import serving_request_operands
+    a, b = serving_request_operands(r)
+    return r, a, b
+
+
+def _generate_serve(args):
+    """Requests of the served stream and of its small stratum, with their
+    operands generated on a host process pool (16 workers at most)."""
+    import multiprocessing as mp
+    from synth import serving_stream
+    t = time.perf_counter()
+    reqs = serving_stream(args.requests, args.seed)
+    small = serving_stream(args.small_requests, args.seed + 1000, max_flop=2 ** 20)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        main_ops = pool.map(_gen_request, reqs, chunksize=4)
+        small_ops = pool.map(_gen_request, small, chunksize=4)
+    log(f"serve: {len(reqs)} + {len(small)} requests generated in {time.perf_counter() - t:.1f}s "
+        f"on {workers} processes")
+    return main_ops, small_ops
+
+
+def _upload(sp, ops, dev):
+    from paper_1804_01698_amd.serve import Request
+    return [Request(r.rid, r.arrival_s, sp.DeviceCSR.from_host(a, device=dev), sp.DeviceCSR.from_host(b, device=dev),
+                    r.sorted_out) for r, a, b in ops]
+
+
+def bench_serve(args, sp, dev, main_ops, small_ops):
+    """Served stream (request-level parallelism on one GPU).
+
+    (i) saturation capacity mu: every request queued at t = 0; then the same
+    stream replayed in real time at lambda = 0.5 mu and 0.9 mu (Poisson
+    arrivals rescaled).  (ii) small stratum (requests with n*d^2 <= 2^20):
+    the server's batched path against one launch sequence per product."""
+    import torch
+    from paper_1804_01698_amd.serve import Request, Server, serial_products
+    budget = int(args.budget_gb * 1e9)
+    t_gen = time.perf_counter()
+    reqs = [r for r, _, _ in main_ops]
+    dreqs = _upload(sp, main_ops, dev)
+    del main_ops
+    torch.cuda.synchronize()
+    operand_bytes = sum(r.A.rpts.numel() * 4 + r.A.nnz * 12 + r.B.rpts.numel() * 4 + r.B.nnz * 12 for r in dreqs)
+    log(f"serve: {len(dreqs)} requests uploaded in {time.perf_counter() - t_gen:.1f}s, "
+        f"operands {operand_bytes / 1e9:.2f} GB")
+
+    # warm-up: kernels loaded, allocator primed
+    Server(budget).run(dreqs[:32], realtime=False)
+    sat = Server(budget).run(dreqs, realtime=False)
+    ssum = sat.summary()
+    mu = ssum["products_per_s"]
+    log(f"serve saturation: {ssum}")
+    base_rate = len(reqs) / max(reqs[-1].arrival_s, 1e-9)
+    loads = {}
+    for frac in (0.5, 0.9):
+        lam = frac * mu
+        scale = base_rate / lam
+        rq = [Request(r.rid, r.arrival_s * scale, r.A, r.B, r.sorted_out) for r in dreqs]
+        rep = Server(budget).run(rq, realtime=True)
+        loads[f"{frac}mu"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.summary().items()}
+        loads[f"{frac}mu"]["lambda_per_s"] = round(lam, 1)
+        log(f"serve at {frac} mu: {loads[f'{frac}mu']}")
+    del dreqs
+
+    small = [r for r, _, _ in small_ops]
+    dsmall = _upload(sp, small_ops, dev)
+    Server(budget).run(dsmall[:16], realtime=False)
+    serial_products(dsmall[:16])
+    # the batched path as a caller uses it: upload the batch description, analyse,
+    # run, synchronise; products with a row outside the batched range go through
+    # the plan path one at a time
+    def batched_direct():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bt = sp.Batch([r.A for r in dsmall], [r.B for r in dsmall], [r.sorted_out for r in dsmall])
+        bt.run()
+        outs = bt.outputs()
+        rest = [r for r, c in zip(dsmall, outs) if c is None]
+        serial_products(rest)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, bt, len(rest)
+
+    batched_direct()
+    best = {}
+    for _ in range(3):
+        tb, bt, nrest = batched_direct()
+        rb = Server(budget).run(dsmall, realtime=False)
+        tsv = max(c.done_s for c in rb.completions)
+        ts = serial_products(dsmall)
+        for k, v in (("batched", tb), ("server", tsv), ("serial", ts)):
+            best[k] = min(best.get(k, v), v)
+    # the run alone (kernels only; what a captured graph replays)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(10):
+        bt.run()
+    torch.cuda.synchronize()
+    t_run = (time.perf_counter() - t) / 10
+    sm = rb.summary()
+    out = {
+        "metric": METRIC,
+        "value": round(mu, 2),
+        "unit": "products/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(sat.wall_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serve: {WORKLOADS['serve']['desc']}", "requests": len(reqs), "seed": args.seed,
+                   "budget_gb": args.budget_gb, "operand_gb": round(operand_bytes / 1e9, 3)},
+        "saturation": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in ssum.items()},
+        "load": loads,
+        "small_stratum": {"requests": len(small), "outside_batched_range": nrest,
+                          "batched_s": round(best["batched"], 5), "serial_s": round(best["serial"], 5),
+                          "speedup": round(best["serial"] / best["batched"], 2),
+                          "batch_run_only_s": round(t_run, 5),
+                          "server_s": round(best["server"], 5),
+                          "server_speedup": round(best["serial"] / best["server"], 2),
+                          "server_batched": sm["batched"], "server_planned": sm["planned"]},
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

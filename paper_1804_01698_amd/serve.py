@@ -146,8 +146,9 @@ class Server:
     them all at once with ``realtime=False``) and returns a ServeReport."""
 
     def __init__(self, mem_budget_bytes: int, on_result: Optional[Callable[[Request, DeviceCSR], None]] = None,
-                 max_batch: int = 4096, batch_flop_max: int = 1 << 26):
+                 max_batch: int = 4096, batch_flop_max: int = 1 << 26, plan_workers: int = 2):
         self.gate = MemoryGate(mem_budget_bytes)
+        self.plan_workers = max(1, plan_workers)
         self.on_result = on_result
         self.max_batch = max_batch
         self.batch_flop_max = batch_flop_max
@@ -183,7 +184,8 @@ class Server:
                     for r in reqs:
                         self._done(r, "batch", 0, 0, -10, None)
                     self._errors.append(repr(e))
-        self._plan_q_put(None)
+        for _ in range(self.plan_workers):
+            self._plan_q_put(None)
 
     def _drain(self) -> List[Request]:
         """Queued requests for one batch: at most max_batch, and as many as keep
@@ -272,8 +274,7 @@ class Server:
             self._plan_q.append(item)
             self._pcv.notify_all()
 
-    def _plan_worker(self):
-        stream = self._sp
+    def _plan_worker(self, stream):
         with torch.cuda.stream(stream):
             while True:
                 with self._pcv:
@@ -338,15 +339,17 @@ class Server:
         self._batches = 0
         self._batch_sizes: List[int] = []
         self._sb = torch.cuda.Stream()
-        self._sp = torch.cuda.Stream()
+        plan_streams = [torch.cuda.Stream() for _ in range(self.plan_workers)]
         torch.cuda.synchronize()
         torch.cuda.reset_peak_memory_stats()
         order = sorted(requests, key=lambda r: r.arrival_s)
         tb = threading.Thread(target=self._batch_worker, name="spgemm-batch", daemon=True)
-        tp = threading.Thread(target=self._plan_worker, name="spgemm-plan", daemon=True)
+        tps = [threading.Thread(target=self._plan_worker, args=(st,), name=f"spgemm-plan{i}", daemon=True)
+               for i, st in enumerate(plan_streams)]
         self._t0 = time.perf_counter()
         tb.start()
-        tp.start()
+        for t in tps:
+            t.start()
         for r in order:
             if realtime:
                 wait = r.arrival_s - (time.perf_counter() - self._t0)
@@ -361,7 +364,8 @@ class Server:
             self._closed = True
             self._cv.notify_all()
         tb.join()
-        tp.join()
+        for t in tps:
+            t.join()
         wall = time.perf_counter() - self._t0
         torch.cuda.synchronize()
         if self._errors:
