@@ -103,17 +103,48 @@ typedef struct spgemm_plan_s *spgemm_plan_t;
 size_t spgemm_plan_scratch_bytes(int nprod, const spgemm_csr *A);
 
 /*
+ * Tunables of a plan: the hash of the LDS tables and the row bins (Section
+ * 4.2.1 hashes a column id by multiplying it by a constant; Fig. 5 sizes a
+ * table from the rows it serves).  Rows are binned by their key bound
+ * x = min(row flop, ncols) in the symbolic phase and by nnz(c_i) in the
+ * numeric phase; bin b (1..9) serves bounds in (max[b-2], max[b-1]] with an
+ * LDS table of
+ *   symbolic: 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384 keys
+ *   numeric:  64, 128, 256, 512, 1024, 2048, 4096, 8192, 11264 entries
+ * for b = 1..9.  Limits must be positive, non-decreasing, at most their
+ * table's size (a fuller table still works, with longer probes), and the
+ * ninth must be 8448 (rows above it take the heavy-row path).  hash_mul is
+ * the odd multiplier of the hash; 0 sends every key to the first bucket (a
+ * worst case, for tests).  The defaults (spgemm_config_default) fill each
+ * table at most half.
+ */
+typedef struct {
+    uint32_t hash_mul;
+    int32_t sym_max[9];
+    int32_t num_max[9];
+} spgemm_config;
+
+/* The default configuration. */
+void spgemm_config_default(spgemm_config *cfg);
+
+/* SPGEMM_OK if cfg satisfies the rules above, else SPGEMM_ERR_INVALID_ARG. */
+int spgemm_config_check(const spgemm_config *cfg);
+
+/*
  * Plan nprod independent products C[p] = A[p]*B[p] (nprod >= 1; A and B are
  * host arrays of nprod descriptors).  Computes row flop and groups rows by
  * flop on the device, then reads the group sizes back (synchronises stream).
  *   plan_scratch     device buffer of spgemm_plan_scratch_bytes(nprod, A)
  *                    bytes, kept alive until spgemm_free
  *   workspace_bytes  out: bytes of device workspace spgemm_symbolic needs
+ *   cfg              tunables (NULL: spgemm_config_default); an invalid
+ *                    cfg gives SPGEMM_ERR_INVALID_ARG
  * Values are not read here.  On error *out is NULL.
  */
 int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm_csr *B,
                 spgemm_dtype dtype, unsigned flags, void *plan_scratch, hipStream_t stream,
-                size_t *workspace_bytes);
+                size_t *workspace_bytes,
+                const spgemm_config *cfg);
 
 /*
  * Symbolic phase.  Writes rpts_C[p][0..A[p].nrows] (device int64, caller-owned,

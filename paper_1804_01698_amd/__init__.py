@@ -10,6 +10,8 @@ from .binding import (
     BATCH_XMAX,
     batch_arena_bytes,
     batch_scratch_bytes,
+    config_ok,
+    default_config,
     plan_scratch_bytes,
     DeviceCSR,
     Plan,
@@ -26,6 +28,6 @@ from .binding import (
 )
 
 __all__ = [
-    "Batch", "BATCH_XMAX", "batch_arena_bytes", "batch_scratch_bytes", "plan_scratch_bytes", "DeviceCSR", "Plan", "SpgemmError", "F64", "I64", "SORTED", "VALIDATE", "lib_path",
+    "Batch", "BATCH_XMAX", "batch_arena_bytes", "batch_scratch_bytes", "plan_scratch_bytes", "config_ok", "default_config", "DeviceCSR", "Plan", "SpgemmError", "F64", "I64", "SORTED", "VALIDATE", "lib_path",
     "masked_sum_i64", "spgemm", "stream_copy", "triangle_count",
 ]

@@ -37,6 +37,10 @@ class _Stats(ctypes.Structure):
                 ("probe_overflow", ctypes.c_int64)]
 
 
+class _Config(ctypes.Structure):
+    _fields_ = [("hash_mul", ctypes.c_uint32), ("sym_max", ctypes.c_int32 * 9), ("num_max", ctypes.c_int32 * 9)]
+
+
 class _KTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("ms", ctypes.c_double), ("launches", ctypes.c_int64),
                 ("alg_bytes", ctypes.c_double)]
@@ -54,7 +58,11 @@ def _load():
     lib.spgemm_plan_scratch_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr)]
     lib.spgemm_plan.restype = ctypes.c_int
     lib.spgemm_plan.argtypes = [pp, ctypes.c_int, ctypes.POINTER(_Csr), ctypes.POINTER(_Csr), ctypes.c_int,
-                                ctypes.c_uint, P, P, ctypes.POINTER(ctypes.c_size_t)]
+                                ctypes.c_uint, P, P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_Config)]
+    lib.spgemm_config_default.restype = None
+    lib.spgemm_config_default.argtypes = [ctypes.POINTER(_Config)]
+    lib.spgemm_config_check.restype = ctypes.c_int
+    lib.spgemm_config_check.argtypes = [ctypes.POINTER(_Config)]
     lib.spgemm_symbolic.restype = ctypes.c_int
     lib.spgemm_symbolic.argtypes = [P, P, pp, i64p]
     lib.spgemm_numeric.restype = ctypes.c_int
@@ -149,6 +157,30 @@ def _dtype_code(A: DeviceCSR, B: DeviceCSR) -> int:
     raise TypeError("values must both be float64 or both be int64")
 
 
+def default_config() -> dict:
+    """The library's default plan configuration as a dict
+    {hash_mul, sym_max[9], num_max[9]} (see spgemm_config)."""
+    c = _Config()
+    _lib.spgemm_config_default(ctypes.byref(c))
+    return {"hash_mul": int(c.hash_mul), "sym_max": list(c.sym_max), "num_max": list(c.num_max)}
+
+
+def _config_struct(cfg: Optional[dict]) -> Optional[_Config]:
+    if cfg is None:
+        return None
+    c = _Config()
+    c.hash_mul = int(cfg["hash_mul"]) & 0xFFFFFFFF
+    for i in range(9):
+        c.sym_max[i] = int(cfg["sym_max"][i])
+        c.num_max[i] = int(cfg["num_max"][i])
+    return c
+
+
+def config_ok(cfg: dict) -> bool:
+    """Whether the library accepts this configuration."""
+    return _lib.spgemm_config_check(ctypes.byref(_config_struct(cfg))) == 0
+
+
 class Plan:
     """One planned batch of products C[p] = A[p] @ B[p] (plan -> symbolic -> numeric).
 
@@ -157,7 +189,7 @@ class Plan:
 
     def __init__(self, As: Sequence[DeviceCSR], Bs: Sequence[DeviceCSR], sorted_output: bool = True,
                  dtype: Optional[int] = None, validate: bool = False, stream=None, timing: bool = False,
-                 defer_workspace: bool = False):
+                 defer_workspace: bool = False, config: Optional[dict] = None):
         if len(As) != len(Bs) or not As:
             raise ValueError("need equal, non-empty lists of operands")
         self.As, self.Bs = list(As), list(Bs)
@@ -173,9 +205,10 @@ class Plan:
         self.plan_scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
         ws = ctypes.c_size_t(0)
         flags = (SORTED if self.sorted else 0) | (VALIDATE if validate else 0) | (TIMING if timing else 0)
+        cs = _config_struct(config)
         st = _lib.spgemm_plan(ctypes.byref(self._h), self.n, self._ca, self._cb, self.dtype, flags,
                               ctypes.c_void_p(self.plan_scratch.data_ptr()), _stream_handle(stream),
-                              ctypes.byref(ws))
+                              ctypes.byref(ws), None if cs is None else ctypes.byref(cs))
         _check(st, "spgemm_plan")
         self.workspace_bytes = int(ws.value)
         self.workspace = None

@@ -83,6 +83,7 @@ struct spgemm_plan_s {
     size_t ws_total = 0;
     bool timing = false;
     int ncu = 256;
+    BinLimits lim = default_limits();
     std::vector<TimedLaunch> tl;
 };
 
@@ -114,6 +115,23 @@ bool csr_ok(const spgemm_csr &a) {
 }
 
 CsrDev dev(const spgemm_csr &a) { return CsrDev{a.nrows, a.ncols, a.nnz, a.rpts, a.cols, a.vals}; }
+
+// Per-bin limits of a config, checked against the table sizes (a limit above
+// its table could leave a probe without a free slot).
+bool limits_from(const spgemm_config *cfg, BinLimits *L) {
+    *L = default_limits();
+    if (!cfg) return true;
+    for (int b = 1; b <= 9; ++b) {
+        const int64_t s = cfg->sym_max[b - 1], n = cfg->num_max[b - 1];
+        if (s < 1 || s > SYM_T[b] || s < L->sym[b - 1]) return false;
+        if (n < 1 || n > NUM_T[b] || n < L->num[b - 1]) return false;
+        L->sym[b] = s;
+        L->num[b] = n;
+    }
+    if (L->sym[9] != WIN_CAP || L->num[9] != WIN_CAP) return false;
+    L->hmul = cfg->hash_mul;
+    return true;
+}
 
 size_t plan_scratch_one(int64_t m) { return PLAN_HDR_BYTES + align_up((size_t)m * 4); }
 
@@ -148,8 +166,23 @@ const char *spgemm_strerror(int status) {
     }
 }
 
+void spgemm_config_default(spgemm_config *cfg) {
+    if (!cfg) return;
+    cfg->hash_mul = HASH_MUL_DEFAULT;
+    for (int b = 1; b <= 9; ++b) {
+        cfg->sym_max[b - 1] = (int32_t)SYM_XMAX[b];
+        cfg->num_max[b - 1] = (int32_t)NUM_XMAX[b];
+    }
+}
+
+int spgemm_config_check(const spgemm_config *cfg) {
+    BinLimits L;
+    return (cfg && limits_from(cfg, &L)) ? SPGEMM_OK : SPGEMM_ERR_INVALID_ARG;
+}
+
 int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm_csr *B, spgemm_dtype dtype,
-                unsigned flags, void *plan_scratch, hipStream_t stream, size_t *workspace_bytes) {
+                unsigned flags, void *plan_scratch, hipStream_t stream, size_t *workspace_bytes,
+                const spgemm_config *cfg) {
     if (!out) return SPGEMM_ERR_INVALID_ARG;
     *out = nullptr;
     if (nprod <= 0 || !A || !B || !workspace_bytes) return SPGEMM_ERR_INVALID_ARG;
@@ -160,9 +193,12 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
         if (A[p].ncols != B[p].nrows) return SPGEMM_ERR_SHAPE;
     }
     if (!plan_scratch) return SPGEMM_ERR_INVALID_ARG;
+    BinLimits lim;
+    if (!limits_from(cfg, &lim)) return SPGEMM_ERR_INVALID_ARG;
 
     spgemm_plan_s *pl = new (std::nothrow) spgemm_plan_s();
     if (!pl) return SPGEMM_ERR_HOST_ALLOC;
+    pl->lim = lim;
     pl->nprod = nprod;
     pl->dtype = (int)dtype;
     pl->flags = flags;
@@ -210,7 +246,7 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     for (int p = 0; p < nprod; ++p) {
         Prod &q = pl->prods[p];
         hipError_t e = timed(pl, "row_flop", 12.0 * q.A.nnz + 8.0 * q.m,
-                             [&] { return launch_row_flop(q.A, q.B, q.flop, q.phdr, stream); });
+                             [&] { return launch_row_flop(q.A, q.B, q.flop, q.phdr, pl->lim, stream); });
         if (e == hipSuccess) e = launch_count_long_b(q.B, q.phdr, stream);
         if (e != hipSuccess) return fail(hip_fail(e, "row_flop"));
     }
@@ -296,7 +332,7 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
         HIPCK(timed(pl, "sym_scatter", 8.0 * m,
                     [&] {
                         return launch_sym_scatter(m, q.flop, q.B.ncols, off, perm, nnz, q.at<int32_t>(q.o_slot),
-                                                  q.wh, s);
+                                                  q.wh, pl->lim, s);
                     }),
               "sym_scatter");
         if (q.nbm > 0) {
@@ -324,7 +360,7 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
                 char name[32];
                 snprintf(name, sizeof(name), "sym_hash_%d", SYM_T[b]);
                 HIPCK(timed(pl, name, rows_bytes,
-                            [&] { return launch_sym_bin(b, nr, perm, off.v[b], q.A, q.B, nnz, q.wh, s); }),
+                            [&] { return launch_sym_bin(b, nr, perm, off.v[b], q.A, q.B, nnz, q.wh, pl->lim.hmul, s); }),
                       "sym_hash");
             }
         }
@@ -334,7 +370,7 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
         HIPCK(timed(pl, "num_hist", 12.0 * m,
                     [&] {
                         return launch_num_hist(m, nnz, q.flop, q.A.rpts, q.at<int32_t>(q.o_slot),
-                                               q.at<HeavyRow>(q.o_heavy), q.wh, s);
+                                               q.at<HeavyRow>(q.o_heavy), q.wh, pl->lim, s);
                     }),
               "num_hist");
         if (q.nbm > 0) {
@@ -365,7 +401,7 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
         HIPCK(timed(pl, "num_scatter", 8.0 * q.m,
                     [&] {
                         return launch_num_scatter((int)q.m, q.at<int32_t>(q.o_nnz), off, q.at<int32_t>(q.o_perm_num),
-                                                  q.wh, s);
+                                                  q.wh, pl->lim, s);
                     }),
               "num_scatter");
     }
@@ -412,7 +448,7 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
             HIPCK(timed(pl, name, bytes,
                         [&] {
                             return launch_num_bin(b, pl->dtype, sorted, nr, perm, q.num_off[b], q.A, q.B, q.rpts_C,
-                                                  cols_C[p], vals_C[p], q.wh, s);
+                                                  cols_C[p], vals_C[p], q.wh, pl->lim.hmul, s);
                         }),
                   "num_hash");
         }

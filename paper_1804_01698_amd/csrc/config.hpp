@@ -46,6 +46,43 @@ constexpr int NUM_G[NNB] = {0, 64, 64, 64, 128, 256, 256, 512, 1024, 1024, 1024}
 constexpr int NUM_T[NNB] = {0, 64, 128, 256, 512, 1024, 2048, 4096, 8192, WIN_TABLE, WIN_TABLE};
 constexpr int64_t NUM_XMAX[NNB] = {0, 32, 64, 128, 256, 512, 1024, 2048, 4096, WIN_CAP, INT64_MAX};
 
+// Bin limits of one plan (tunable; see spgemm_config): bin b of the symbolic
+// phase takes rows with sym[b-1] < min(flop, ncols) <= sym[b], bin b of the
+// numeric phase rows with num[b-1] < nnz(c_i) <= num[b].  A limit never
+// exceeds its bin's table size (so a probe always finds room); bin 9 ends at
+// WIN_CAP in both phases (the heavy-row boundary is structural).  hmul is
+// the odd multiplier of the column hash.
+constexpr uint32_t HASH_MUL_DEFAULT = 2654435761u;
+struct BinLimits {
+    int64_t sym[NSB];
+    int64_t num[NNB];
+    uint32_t hmul;
+    uint32_t pad;
+};
+
+__host__ __device__ inline BinLimits default_limits() {
+    BinLimits L{};
+    for (int b = 0; b < NSB; ++b) L.sym[b] = SYM_XMAX[b];
+    for (int b = 0; b < NNB; ++b) L.num[b] = NUM_XMAX[b];
+    L.hmul = HASH_MUL_DEFAULT;
+    return L;
+}
+
+__host__ __device__ inline int sym_bin_l(uint64_t flop, int64_t ncols, const BinLimits &L) {
+    uint64_t x = flop < (uint64_t)ncols ? flop : (uint64_t)ncols;
+    if (x == 0) return 0;
+    for (int b = 1; b < SYM_BITMAP_BIN; ++b)
+        if (x <= (uint64_t)L.sym[b]) return b;
+    return SYM_BITMAP_BIN;
+}
+
+__host__ __device__ inline int num_bin_l(int64_t nnz, const BinLimits &L) {
+    if (nnz <= 0) return 0;
+    for (int b = 1; b < NUM_HEAVY_BIN; ++b)
+        if (nnz <= L.num[b]) return b;
+    return NUM_HEAVY_BIN;
+}
+
 __host__ __device__ inline int sym_bin(uint64_t flop, int64_t ncols) {
     uint64_t x = flop < (uint64_t)ncols ? flop : (uint64_t)ncols;
     if (x == 0) return 0;

@@ -80,10 +80,12 @@ __device__ __forceinline__ void block_sync() {
 
 // ---- LDS hash tables ----------------------------------------------------------
 // Keys are column ids (>= 0); an empty slot holds -1.  The slot is the high
-// half of (key * 2654435761) * T, a multiplicative hash folded onto any table
-// size T; collisions are resolved by linear probing with wrap-around.
-__device__ __forceinline__ uint32_t hash_slot(int key, uint32_t T) {
-    const uint32_t h = (uint32_t)key * 2654435761u;
+// half of (key * mul mod 2^32) * T, a multiplicative hash (Section 4.2.1:
+// the key times a constant) folded onto any table size T; collisions are
+// resolved by linear probing with wrap-around.  mul = 0 sends every key to
+// slot 0 (a worst case for tests).
+__device__ __forceinline__ uint32_t hash_slot(int key, uint32_t T, uint32_t mul = HASH_MUL_DEFAULT) {
+    const uint32_t h = (uint32_t)key * mul;
     return (uint32_t)(((uint64_t)h * T) >> 32);
 }
 
@@ -165,9 +167,10 @@ __device__ __forceinline__ int bucket_pick(int4 k, int key, bool &empty_hit) {
 // Insert key (and with NUM add x to its value); returns 1 if the key is new.
 // A probe that runs past every bucket without room sets ovf and gives up.
 template <bool NUM, typename V>
-__device__ __forceinline__ int bkt_insert(int *keys, V *vals, uint32_t T, int key, V x, int &ovf) {
+__device__ __forceinline__ int bkt_insert(int *keys, V *vals, uint32_t T, int key, V x, int &ovf,
+                                          uint32_t mul = HASH_MUL_DEFAULT) {
     const uint32_t NB = T / BKT;
-    uint32_t b = hash_slot(key, NB);
+    uint32_t b = hash_slot(key, NB, mul);
     for (uint32_t it = 0; it < NB + T; ++it) {
         __asm__ __volatile__("" ::: "memory");   // re-read the bucket every round
         const int4 k = lds_load4(&keys[b * BKT]);

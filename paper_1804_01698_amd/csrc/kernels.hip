@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nrows, int64_t ncols, 
 __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restrict__ rA,
                                                   const int32_t *__restrict__ cA,
                                                   const int32_t *__restrict__ rB, int64_t ncolsB,
-                                                  uint32_t *__restrict__ flop_out, PlanHdr *hdr) {
+                                                  uint32_t *__restrict__ flop_out, PlanHdr *hdr, BinLimits L) {
     __shared__ int s_rp[257];
     __shared__ unsigned long long s_f[256];
     __shared__ unsigned long long s_rows[NSB], s_flop[NSB], s_nnza[NSB];
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restri
     if (tid < nr) {
         const unsigned long long f = s_f[tid];
         flop_out[r0 + tid] = f > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)f;
-        const int b = sym_bin(f, ncolsB);
+        const int b = sym_bin_l(f, ncolsB, L);
         atomicAdd(&s_rows[b], 1ull);
         atomicAdd(&s_flop[b], f);
         atomicAdd(&s_nnza[b], (unsigned long long)(s_rp[tid + 1] - s_rp[tid]));
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_sym_scatter(int m, const uint32_t *__re
                                                      int64_t ncolsB, BinOffsets off,
                                                      int32_t *__restrict__ perm,
                                                      int32_t *__restrict__ nnz_row,
-                                                     int32_t *__restrict__ slot_of, WsHdr *wh) {
+                                                     int32_t *__restrict__ slot_of, WsHdr *wh, BinLimits L) {
     __shared__ unsigned int s_cnt[NSB], s_base[NSB];
     const int tid = threadIdx.x;
     if (tid < NSB) s_cnt[tid] = 0;
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_sym_scatter(int m, const uint32_t *__re
     int b = -1;
     unsigned int r = 0;
     if (i < m) {
-        b = sym_bin(flop[i], ncolsB);
+        b = sym_bin_l(flop[i], ncolsB, L);
         if (b == 0) nnz_row[i] = 0;
         else r = atomicAdd(&s_cnt[b], 1u);
     }
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_num_hist(int m, const int32_t *__restri
                                                   const uint32_t *__restrict__ flop,
                                                   const int32_t *__restrict__ rA,
                                                   const int32_t *__restrict__ slot_of,
-                                                  HeavyRow *__restrict__ heavy, WsHdr *wh) {
+                                                  HeavyRow *__restrict__ heavy, WsHdr *wh, BinLimits L) {
     __shared__ unsigned long long s_rows[NNB], s_flop[NNB], s_nnza[NNB], s_nnzc[NNB];
     const int tid = threadIdx.x;
     if (tid < NNB) { s_rows[tid] = 0; s_flop[tid] = 0; s_nnza[tid] = 0; s_nnzc[tid] = 0; }
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_num_hist(int m, const int32_t *__restri
     const int i = blockIdx.x * 256 + tid;
     if (i < m) {
         const int nz = nnz_row[i];
-        const int b = num_bin(nz);
+        const int b = num_bin_l(nz, L);
         atomicAdd(&s_rows[b], 1ull);
         atomicAdd(&s_flop[b], (unsigned long long)flop[i]);
         atomicAdd(&s_nnza[b], (unsigned long long)(rA[i + 1] - rA[i]));
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_num_hist(int m, const int32_t *__restri
 
 __global__ __launch_bounds__(256) void k_num_scatter(int m, const int32_t *__restrict__ nnz_row,
                                                      BinOffsets off, int32_t *__restrict__ perm,
-                                                     WsHdr *wh) {
+                                                     WsHdr *wh, BinLimits L) {
     __shared__ unsigned int s_cnt[NNB], s_base[NNB];
     const int tid = threadIdx.x;
     if (tid < NNB) s_cnt[tid] = 0;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_num_scatter(int m, const int32_t *__res
     int b = -1;
     unsigned int r = 0;
     if (i < m) {
-        b = num_bin(nnz_row[i]);
+        b = num_bin_l(nnz_row[i], L);
         if (b > 0 && b < NUM_HEAVY_BIN) r = atomicAdd(&s_cnt[b], 1u);
         else b = -1;
     }
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
                                                 const int32_t *__restrict__ cA,
                                                 const int32_t *__restrict__ rB,
                                                 const int32_t *__restrict__ cB,
-                                                int32_t *__restrict__ nnz_row, WsHdr *wh) {
+                                                int32_t *__restrict__ nnz_row, WsHdr *wh, uint32_t hmul) {
     __shared__ __align__(16) int tab[T];
     __shared__ SegLds<G, false, double> sg;
     const int tid = threadIdx.x;
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
             for (int u = 0; u < U; ++u) col[u] = ok[u] ? cB[q[u]] : 0;
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf);
+                if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hmul);
         });
     __syncthreads();
     int total;
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
                                                 const V *__restrict__ vB,
                                                 const int64_t *__restrict__ rpts_C,
                                                 int32_t *__restrict__ cC, V *__restrict__ vC,
-                                                WsHdr *wh) {
+                                                WsHdr *wh, uint32_t hmul) {
     __shared__ __align__(16) int keys[T];
     __shared__ V vals[T];
     __shared__ SegLds<G, true, V> sg;
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf);
+                if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf, hmul);
         });
     __syncthreads();
     if (ovf) {
@@ -777,39 +777,41 @@ hipError_t launch_validate(const CsrDev &a, int *err, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, PlanHdr *hdr, hipStream_t s) {
+hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, PlanHdr *hdr, const BinLimits &L,
+                           hipStream_t s) {
     if (A.nrows == 0) return hipSuccess;
-    k_row_flop<<<grid1(A.nrows, 256), 256, 0, s>>>((int)A.nrows, A.rpts, A.cols, B.rpts, B.ncols, flop, hdr);
+    k_row_flop<<<grid1(A.nrows, 256), 256, 0, s>>>((int)A.nrows, A.rpts, A.cols, B.rpts, B.ncols, flop, hdr, L);
     return hipGetLastError();
 }
 
 hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const BinOffsets &off,
-                              int32_t *perm, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh, hipStream_t s) {
+                              int32_t *perm, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh, const BinLimits &L,
+                              hipStream_t s) {
     if (m == 0) return hipSuccess;
-    k_sym_scatter<<<grid1(m, 256), 256, 0, s>>>(m, flop, ncolsB, off, perm, nnz_row, slot_of, wh);
+    k_sym_scatter<<<grid1(m, 256), 256, 0, s>>>(m, flop, ncolsB, off, perm, nnz_row, slot_of, wh, L);
     return hipGetLastError();
 }
 
 template <int G, int T>
 static void sym_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                       const CsrDev &B, int32_t *nnz_row, WsHdr *wh, hipStream_t s) {
+                       const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, hipStream_t s) {
     constexpr int U = u_for(G, T / 2 + 1);
-    k_sym_hash<G, T, U><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, nnz_row, wh);
+    k_sym_hash<G, T, U><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, nnz_row, wh, hmul);
 }
 
 hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, hipStream_t s) {
+                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     switch (bin) {
-        case 1: sym_hash_l<SYM_G[1], SYM_T[1]>(nrows, perm, off, A, B, nnz_row, wh, s); break;
-        case 2: sym_hash_l<SYM_G[2], SYM_T[2]>(nrows, perm, off, A, B, nnz_row, wh, s); break;
-        case 3: sym_hash_l<SYM_G[3], SYM_T[3]>(nrows, perm, off, A, B, nnz_row, wh, s); break;
-        case 4: sym_hash_l<SYM_G[4], SYM_T[4]>(nrows, perm, off, A, B, nnz_row, wh, s); break;
-        case 5: sym_hash_l<SYM_G[5], SYM_T[5]>(nrows, perm, off, A, B, nnz_row, wh, s); break;
-        case 6: sym_hash_l<SYM_G[6], SYM_T[6]>(nrows, perm, off, A, B, nnz_row, wh, s); break;
-        case 7: sym_hash_l<SYM_G[7], SYM_T[7]>(nrows, perm, off, A, B, nnz_row, wh, s); break;
-        case 8: sym_hash_l<SYM_G[8], SYM_T[8]>(nrows, perm, off, A, B, nnz_row, wh, s); break;
-        case 9: sym_hash_l<SYM_G[9], SYM_T[9]>(nrows, perm, off, A, B, nnz_row, wh, s); break;
+        case 1: sym_hash_l<SYM_G[1], SYM_T[1]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
+        case 2: sym_hash_l<SYM_G[2], SYM_T[2]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
+        case 3: sym_hash_l<SYM_G[3], SYM_T[3]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
+        case 4: sym_hash_l<SYM_G[4], SYM_T[4]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
+        case 5: sym_hash_l<SYM_G[5], SYM_T[5]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
+        case 6: sym_hash_l<SYM_G[6], SYM_T[6]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
+        case 7: sym_hash_l<SYM_G[7], SYM_T[7]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
+        case 8: sym_hash_l<SYM_G[8], SYM_T[8]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
+        case 9: sym_hash_l<SYM_G[9], SYM_T[9]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -841,9 +843,9 @@ hipError_t launch_scan(const int32_t *nnz_row, int m, long long *bsum, int64_t *
 }
 
 hipError_t launch_num_hist(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
-                           const int32_t *slot_of, HeavyRow *heavy, WsHdr *wh, hipStream_t s) {
+                           const int32_t *slot_of, HeavyRow *heavy, WsHdr *wh, const BinLimits &L, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    k_num_hist<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, flop, rA, slot_of, heavy, wh);
+    k_num_hist<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, flop, rA, slot_of, heavy, wh, L);
     return hipGetLastError();
 }
 
@@ -887,34 +889,34 @@ hipError_t launch_gather_vals(int dtype, int64_t n, const int32_t *bperm, const 
 }
 
 hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &off, int32_t *perm, WsHdr *wh,
-                              hipStream_t s) {
+                              const BinLimits &L, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    k_num_scatter<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, off, perm, wh);
+    k_num_scatter<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, off, perm, wh, L);
     return hipGetLastError();
 }
 
 template <int G, int T, bool SORTED, typename V>
 static void num_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                       const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s) {
+                       const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, uint32_t hmul, hipStream_t s) {
     constexpr int U = u_for(G, T / 2 + 1) < 4 ? u_for(G, T / 2 + 1) : 4;
     k_num_hash<G, T, U, SORTED, V><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, (const V *)A.vals, B.rpts, B.cols,
-                                                     (const V *)B.vals, rpts_C, cC, (V *)vC, wh);
+                                                     (const V *)B.vals, rpts_C, cC, (V *)vC, wh, hmul);
 }
 
 template <bool SORTED, typename V>
 static hipError_t num_bin_t(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
                             const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh,
-                            hipStream_t s) {
+                            uint32_t hmul, hipStream_t s) {
     switch (bin) {
-        case 1: num_hash_l<NUM_G[1], NUM_T[1], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, s); break;
-        case 2: num_hash_l<NUM_G[2], NUM_T[2], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, s); break;
-        case 3: num_hash_l<NUM_G[3], NUM_T[3], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, s); break;
-        case 4: num_hash_l<NUM_G[4], NUM_T[4], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, s); break;
-        case 5: num_hash_l<NUM_G[5], NUM_T[5], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, s); break;
-        case 6: num_hash_l<NUM_G[6], NUM_T[6], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, s); break;
-        case 7: num_hash_l<NUM_G[7], NUM_T[7], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, s); break;
-        case 8: num_hash_l<NUM_G[8], NUM_T[8], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, s); break;
-        case 9: num_hash_l<NUM_G[9], NUM_T[9], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, s); break;
+        case 1: num_hash_l<NUM_G[1], NUM_T[1], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
+        case 2: num_hash_l<NUM_G[2], NUM_T[2], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
+        case 3: num_hash_l<NUM_G[3], NUM_T[3], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
+        case 4: num_hash_l<NUM_G[4], NUM_T[4], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
+        case 5: num_hash_l<NUM_G[5], NUM_T[5], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
+        case 6: num_hash_l<NUM_G[6], NUM_T[6], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
+        case 7: num_hash_l<NUM_G[7], NUM_T[7], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
+        case 8: num_hash_l<NUM_G[8], NUM_T[8], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
+        case 9: num_hash_l<NUM_G[9], NUM_T[9], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -922,13 +924,13 @@ static hipError_t num_bin_t(int bin, unsigned nrows, const int32_t *perm, int64_
 
 hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
                           const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
-                          WsHdr *wh, hipStream_t s) {
+                          WsHdr *wh, uint32_t hmul, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     if (dtype == 0)
-        return sorted ? num_bin_t<true, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, s)
-                      : num_bin_t<false, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, s);
-    return sorted ? num_bin_t<true, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, s)
-                  : num_bin_t<false, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, s);
+        return sorted ? num_bin_t<true, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s)
+                      : num_bin_t<false, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s);
+    return sorted ? num_bin_t<true, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s)
+                  : num_bin_t<false, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s);
 }
 
 // Windows leave in ascending column order, so sorted and unsorted output share it.

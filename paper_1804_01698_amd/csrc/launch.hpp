@@ -22,17 +22,19 @@ struct BinOffsets {
 
 
 hipError_t launch_validate(const CsrDev &a, int *err, hipStream_t s);
-hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, PlanHdr *hdr, hipStream_t s);
+hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, PlanHdr *hdr, const BinLimits &L,
+                           hipStream_t s);
 hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const BinOffsets &off,
-                              int32_t *perm, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh, hipStream_t s);
+                              int32_t *perm, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh, const BinLimits &L,
+                              hipStream_t s);
 hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, hipStream_t s);
+                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, hipStream_t s);
 hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
                                int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, hipStream_t s);
 hipError_t launch_scan(const int32_t *nnz_row, int m, long long *bsum, int64_t *rpts_C, WsHdr *wh,
                        hipStream_t s);
 hipError_t launch_num_hist(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
-                           const int32_t *slot_of, HeavyRow *heavy, WsHdr *wh, hipStream_t s);
+                           const int32_t *slot_of, HeavyRow *heavy, WsHdr *wh, const BinLimits &L, hipStream_t s);
 hipError_t launch_count_long_b(const CsrDev &B, PlanHdr *hdr, hipStream_t s);
 hipError_t launch_windows(unsigned nheavy_max, const HeavyRow *heavy, int nchunks, const uint32_t *chunk_cnt,
                           const int64_t *rpts_C, uint32_t *whist, uint32_t *wcur, WinItem *items, unsigned cap,
@@ -41,10 +43,10 @@ hipError_t launch_bucket(const CsrDev &B, int32_t *bc, int32_t *bperm, int32_t *
                          int32_t *idx, int nchunks, WsHdr *wh, hipStream_t s);
 hipError_t launch_gather_vals(int dtype, int64_t n, const int32_t *bperm, const void *vB, void *bv, hipStream_t s);
 hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &off, int32_t *perm, WsHdr *wh,
-                              hipStream_t s);
+                              const BinLimits &L, hipStream_t s);
 hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
                           const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
-                          WsHdr *wh, hipStream_t s);
+                          WsHdr *wh, uint32_t hmul, hipStream_t s);
 hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
                              const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
                              const void *bv, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s);

@@ -46,17 +46,21 @@ def test_host_side_argument_errors(lib):
     h = ctypes.c_void_p()
     ws = ctypes.c_size_t(0)
     st = lib.spgemm_plan(ctypes.byref(h), 1, ctypes.byref(A), ctypes.byref(B), 0, 0,
-                         ctypes.c_void_p(1), None, ctypes.byref(ws))
+                         ctypes.c_void_p(1), None, ctypes.byref(ws), None)
     assert st == -2 and not h.value
-    st = lib.spgemm_plan(None, 1, ctypes.byref(A), ctypes.byref(A), 0, 0, None, None, ctypes.byref(ws))
+    st = lib.spgemm_plan(None, 1, ctypes.byref(A), ctypes.byref(A), 0, 0, None, None, ctypes.byref(ws), None)
     assert st == -1
     B2 = b._Csr(5, 3, 0, 1, None, None)
     st = lib.spgemm_plan(ctypes.byref(h), 1, ctypes.byref(A), ctypes.byref(B2), 7, 0,
-                         ctypes.c_void_p(1), None, ctypes.byref(ws))
+                         ctypes.c_void_p(1), None, ctypes.byref(ws), None)
     assert st == -1                               # bad dtype
     st = lib.spgemm_plan(ctypes.byref(h), 1, ctypes.byref(A), ctypes.byref(B2), 0, 1 << 9,
-                         ctypes.c_void_p(1), None, ctypes.byref(ws))
+                         ctypes.c_void_p(1), None, ctypes.byref(ws), None)
     assert st == -1                               # unknown flag
+    bad = b._config_struct(dict(b.default_config(), sym_max=[64] * 9))
+    st = lib.spgemm_plan(ctypes.byref(h), 1, ctypes.byref(A), ctypes.byref(B2), 0, 0,
+                         ctypes.c_void_p(1), None, ctypes.byref(ws), ctypes.byref(bad))
+    assert st == -1 and not h.value               # invalid config, rejected before any device work
     assert lib.spgemm_symbolic(None, None, None, None) == -1
     assert lib.spgemm_stream_copy(None, None, 15, None) == -1
 
@@ -67,3 +71,25 @@ def test_plan_scratch_bytes(lib):
     n = lib.spgemm_plan_scratch_bytes(2, arr)
     assert n >= 1000 * 4 and n % 256 == 0
     assert lib.spgemm_plan_scratch_bytes(0, arr) == 0
+
+
+def test_config_rules(lib):
+    """spgemm_config: defaults fill each table at most half; limits must be
+    positive, non-decreasing, within their table and end at the heavy-row
+    boundary (checked on the host)."""
+    from paper_1804_01698_amd import binding as b
+    d = b.default_config()
+    sym_t = [64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384]
+    num_t = [64, 128, 256, 512, 1024, 2048, 4096, 8192, 11264]
+    assert d["hash_mul"] % 2 == 1
+    assert d["sym_max"][8] == 8448 and d["num_max"][8] == 8448
+    assert all(2 * x <= t for x, t in zip(d["sym_max"][:8], sym_t[:8]))
+    assert all(2 * x <= t for x, t in zip(d["num_max"][:8], num_t[:8]))
+    assert b.config_ok(d)
+    full = dict(d, sym_max=sym_t[:8] + [8448], num_max=num_t[:8] + [8448])
+    assert b.config_ok(full)                                      # tables filled to the brim
+    assert b.config_ok(dict(d, hash_mul=0))                       # degenerate hash is allowed
+    assert not b.config_ok(dict(d, sym_max=[65] + d["sym_max"][1:]))          # above the 64-key table
+    assert not b.config_ok(dict(d, num_max=d["num_max"][:8] + [8000]))        # must end at 8448
+    assert not b.config_ok(dict(d, sym_max=[32, 16] + d["sym_max"][2:]))      # decreasing
+    assert not b.config_ok(dict(d, num_max=[0] + d["num_max"][1:]))           # not positive
