@@ -461,7 +461,7 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
                             return launch_num_window(pl->dtype, q.hw.n_items, q.at<WinItem>(q.o_items), q.A, q.B,
                                                      q.at<int32_t>(q.o_long_id), q.at<int32_t>(q.o_idx), q.nchunks,
                                                      q.at<int32_t>(q.o_bc), q.at<void>(q.o_bv), cols_C[p],
-                                                     vals_C[p], q.wh, s);
+                                                     vals_C[p], q.wh, pl->ncu, s);
                         }),
                   "num_window");
         }

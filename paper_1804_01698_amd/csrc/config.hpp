@@ -139,6 +139,7 @@ struct WsHdr {
     unsigned int probe_overflow;
     unsigned int n_groups;
     unsigned int pad2_[2];
+    unsigned int win_next[8];   // window claim counters, one per XCD group
 };
 
 // One column window of one heavy row.

@@ -550,31 +550,26 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
     compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
 }
 
-// All column windows of one heavy row, in order, by one block.  A window's
-// output columns are marked first (one bit per column in LDS), their ranks
-// are the exclusive prefix of the bit counts, and the products are then
-// added straight into a dense array of values indexed by rank: no hashing,
-// no probing, and the window leaves in ascending column order.  The slice of
-// B row k inside the window is two loads from k's chunk index, or the whole
-// row (filtered by column) when the row is short.  The row's A entries (when
-// at most 1024) stay in registers across windows.
+// One column window of a heavy row.  The window's output columns are marked
+// first (one bit per column in LDS), their ranks are the exclusive prefix of
+// the bit counts, and the products are then added straight into a dense
+// array of values indexed by rank: no hashing, no probing, and the window
+// leaves in ascending column order.  The slice of B row k inside the window
+// is two loads from k's chunk index, or the whole row (filtered by column)
+// when the row is short.  The row's A entries (when at most 1024) stay in
+// registers for the window.  The output stores are left in flight: the next
+// window's loads overlap them (a block barrier does not wait for stores).
 template <typename V>
-__global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__ items,
-                                                     const int32_t *__restrict__ rA,
-                                                     const int32_t *__restrict__ cA,
-                                                     const V *__restrict__ vA,
-                                                     const int32_t *__restrict__ rB,
-                                                     const int32_t *__restrict__ long_id,
-                                                     const int32_t *__restrict__ idx, int nchunks,
-                                                     const int32_t *__restrict__ bc,
-                                                     const V *__restrict__ bv,
-                                                     int32_t *__restrict__ cC, V *__restrict__ vC,
-                                                     WsHdr *wh) {
+__device__ __forceinline__ void num_window_item(const WinItem it, const int32_t *__restrict__ rA,
+                                                const int32_t *__restrict__ cA, const V *__restrict__ vA,
+                                                const int32_t *__restrict__ rB,
+                                                const int32_t *__restrict__ long_id,
+                                                const int32_t *__restrict__ idx, int nchunks,
+                                                const int32_t *__restrict__ bc, const V *__restrict__ bv,
+                                                int32_t *__restrict__ cC, V *__restrict__ vC,
+                                                unsigned long long *buf, SegLds<1024, true, V> &sg, bool &bad) {
     constexpr int G = 1024;
-    __shared__ __align__(16) unsigned long long buf[RANK_BUDGET];   // words, then values
-    __shared__ SegLds<G, true, V> sg;
     const int tid = threadIdx.x;
-    const WinItem it = items[blockIdx.x];
     const int a0 = rA[it.row], a1 = rA[it.row + 1];
     const bool resident = a1 - a0 <= G;
     int r0 = 0, r1 = 0, li = -1;
@@ -588,7 +583,6 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
     }
     const int nch1 = nchunks + 1;
     uint32_t *w32 = reinterpret_cast<uint32_t *>(buf);   // word w: bits w32[2w], rank prefix w32[2w+1]
-    bool bad = false;
     {
         const int ch_lo = it.ch_lo, ch_hi = it.ch_hi, count = it.count;
         const int nwords = (ch_hi - ch_lo) * WORDS_PER_CHUNK;
@@ -689,6 +683,47 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
             __builtin_nontemporal_store(vals[r], &vC[it.out_pos + r]);
         }
         __syncthreads();
+    }
+}
+
+
+// Numeric phase of the heavy rows: a persistent grid (one block per CU slot)
+// takes windows one after another.  Windows are sorted by first chunk; they
+// are split into eight contiguous ranges, one per group of blocks
+// blockIdx % 8 (workgroups are dealt round-robin over the XCDs, so a group is
+// one XCD and the blocks sharing an L2 read the same column slices of B);
+// a group claims its range's windows in order with an atomic counter and,
+// once done, helps the other groups.
+template <typename V>
+__global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__ items, unsigned nitems,
+                                                     const int32_t *__restrict__ rA,
+                                                     const int32_t *__restrict__ cA,
+                                                     const V *__restrict__ vA,
+                                                     const int32_t *__restrict__ rB,
+                                                     const int32_t *__restrict__ long_id,
+                                                     const int32_t *__restrict__ idx, int nchunks,
+                                                     const int32_t *__restrict__ bc,
+                                                     const V *__restrict__ bv,
+                                                     int32_t *__restrict__ cC, V *__restrict__ vC,
+                                                     WsHdr *wh) {
+    constexpr unsigned NG = 8;
+    __shared__ __align__(16) unsigned long long buf[RANK_BUDGET];   // words, then values
+    __shared__ SegLds<1024, true, V> sg;
+    __shared__ unsigned s_claim;
+    bool bad = false;
+    const unsigned g0 = blockIdx.x % NG;
+    for (unsigned d = 0; d < NG; ++d) {
+        const unsigned g = (g0 + d) % NG;
+        const unsigned lo = (unsigned)((unsigned long long)nitems * g / NG);
+        const unsigned hi = (unsigned)((unsigned long long)nitems * (g + 1) / NG);
+        for (;;) {
+            if (threadIdx.x == 0) s_claim = atomicAdd(&wh->win_next[g], 1u);
+            __syncthreads();
+            const unsigned i = lo + s_claim;
+            __syncthreads();                       // everyone has read s_claim
+            if (i >= hi) break;                    // uniform over the block
+            num_window_item<V>(items[i], rA, cA, vA, rB, long_id, idx, nchunks, bc, bv, cC, vC, buf, sg, bad);
+        }
     }
     if (bad) atomicOr(&wh->err, ERR_COUNT);
 }
@@ -933,18 +968,36 @@ hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const
                   : num_bin_t<false, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s);
 }
 
+__global__ void k_zero_u32n(unsigned *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+template <class K>
+static int blocks_per_cu(K kern, int G) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, G, 0) != hipSuccess || occ < 1) occ = 1;
+    return occ;
+}
+
 // Windows leave in ascending column order, so sorted and unsorted output share it.
 hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
                              const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
-                             const void *bv, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s) {
+                             const void *bv, int32_t *cC, void *vC, WsHdr *wh, int ncu, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    if (dtype == 0)
-        k_num_window<double><<<nitems, 1024, 0, s>>>(items, A.rpts, A.cols, (const double *)A.vals, B.rpts, long_id,
-                                                     idx, nchunks, bc, (const double *)bv, cC, (double *)vC, wh);
-    else
-        k_num_window<unsigned long long><<<nitems, 1024, 0, s>>>(
-            items, A.rpts, A.cols, (const unsigned long long *)A.vals, B.rpts, long_id, idx, nchunks, bc,
+    k_zero_u32n<<<1, 64, 0, s>>>(wh->win_next, 8);
+    if (dtype == 0) {
+        static const int occ = blocks_per_cu(k_num_window<double>, 1024);
+        const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
+        k_num_window<double><<<grid, 1024, 0, s>>>(items, nitems, A.rpts, A.cols, (const double *)A.vals, B.rpts,
+                                                   long_id, idx, nchunks, bc, (const double *)bv, cC, (double *)vC,
+                                                   wh);
+    } else {
+        static const int occ = blocks_per_cu(k_num_window<unsigned long long>, 1024);
+        const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
+        k_num_window<unsigned long long><<<grid, 1024, 0, s>>>(
+            items, nitems, A.rpts, A.cols, (const unsigned long long *)A.vals, B.rpts, long_id, idx, nchunks, bc,
             (const unsigned long long *)bv, cC, (unsigned long long *)vC, wh);
+    }
     return hipGetLastError();
 }
 
