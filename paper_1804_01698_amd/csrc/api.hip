@@ -377,9 +377,9 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
             HIPCK(timed(pl, "windows", 8.0 * q.nbm * q.nchunks,
                         [&] {
                             return launch_windows((unsigned)q.nbm, q.at<HeavyRow>(q.o_heavy), q.nchunks,
-                                                  q.at<uint32_t>(q.o_chunk), q.rpts_C, q.at<uint32_t>(q.o_whist),
-                                                  q.at<uint32_t>(q.o_whist) + q.nchunks, q.at<WinItem>(q.o_items),
-                                                  q.items_cap, q.wh, s);
+                                                  q.at<uint32_t>(q.o_chunk), q.rpts_C, q.A.rpts,
+                                                  q.at<uint32_t>(q.o_whist), q.at<uint32_t>(q.o_whist) + q.nchunks,
+                                                  q.at<WinItem>(q.o_items), q.items_cap, q.wh, s);
                         }),
                   "windows");
         }

@@ -149,6 +149,7 @@ struct WinItem {
     int32_t ch_hi;      // last chunk (exclusive)
     int32_t count;      // output entries in the window (from the symbolic bitmap)
     int64_t out_pos;    // absolute position in cols_C / vals_C
+    int32_t a0, a1;     // the row's entries of A: [a0, a1)
 };
 
 struct HeavyRow {

@@ -411,6 +411,7 @@ __global__ __launch_bounds__(1024) void k_win_scan(uint32_t *__restrict__ whist,
 __global__ __launch_bounds__(256) void k_win_emit(const HeavyRow *__restrict__ heavy, int nchunks,
                                                   const uint32_t *__restrict__ chunk_cnt,
                                                   const int64_t *__restrict__ rpts_C,
+                                                  const int32_t *__restrict__ rA,
                                                   const uint32_t *__restrict__ wpos, uint32_t *__restrict__ wcur,
                                                   WinItem *__restrict__ items, unsigned cap, WsHdr *wh) {
     const unsigned h = blockIdx.x * 256 + threadIdx.x;
@@ -418,9 +419,10 @@ __global__ __launch_bounds__(256) void k_win_emit(const HeavyRow *__restrict__ h
     const HeavyRow hr = heavy[h];
     const uint32_t *cc = chunk_cnt + (size_t)hr.slot * nchunks;
     int64_t pos = rpts_C[hr.row];
+    const int a0 = rA[hr.row], a1 = rA[hr.row + 1];
     for_each_window(cc, nchunks, [&](int lo, int hi, int cnt) {
         const unsigned at = wpos[lo] + atomicAdd(&wcur[lo], 1u);
-        if (at < cap) items[at] = WinItem{hr.row, lo, hi, cnt, pos};
+        if (at < cap) items[at] = WinItem{hr.row, lo, hi, cnt, pos, a0, a1};
         pos += cnt;
     });
 }
@@ -550,66 +552,115 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
     compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
 }
 
-// One column window of a heavy row.  The window's output columns are marked
-// first (one bit per column in LDS), their ranks are the exclusive prefix of
-// the bit counts, and the products are then added straight into a dense
-// array of values indexed by rank: no hashing, no probing, and the window
-// leaves in ascending column order.  The slice of B row k inside the window
-// is two loads from k's chunk index, or the whole row (filtered by column)
-// when the row is short.  The row's A entries (when at most 1024) stay in
-// registers for the window.  The output stores are left in flight: the next
-// window's loads overlap them (a block barrier does not wait for stores).
-template <typename V>
-__device__ __forceinline__ void num_window_item(const WinItem it, const int32_t *__restrict__ rA,
-                                                const int32_t *__restrict__ cA, const V *__restrict__ vA,
-                                                const int32_t *__restrict__ rB,
-                                                const int32_t *__restrict__ long_id,
-                                                const int32_t *__restrict__ idx, int nchunks,
-                                                const int32_t *__restrict__ bc, const V *__restrict__ bv,
-                                                int32_t *__restrict__ cC, V *__restrict__ vC,
-                                                unsigned long long *buf, SegLds<1024, true, V> &sg, bool &bad) {
-    constexpr int G = 1024;
-    const int tid = threadIdx.x;
-    const int a0 = rA[it.row], a1 = rA[it.row + 1];
-    const bool resident = a1 - a0 <= G;
-    int r0 = 0, r1 = 0, li = -1;
-    V a = V(0);
-    if (resident && a0 + tid < a1) {
-        const int k = cA[a0 + tid];
-        a = vA[a0 + tid];
-        r0 = rB[k];
-        r1 = rB[k + 1];
-        li = long_id[k];
+// Claim of the next window for the block (thread 0 only): windows, sorted by
+// first chunk, are split into eight contiguous ranges, one per group of blocks
+// blockIdx % 8 (workgroups are dealt round-robin over the XCDs, so a group is
+// one XCD and the blocks sharing an L2 read the same column slices of B); a
+// block takes its group's windows in order and then helps the other groups.
+constexpr unsigned WIN_NONE = 0xFFFFFFFFu;
+
+__device__ __forceinline__ unsigned win_claim(WsHdr *wh, unsigned nitems, unsigned g0, unsigned &d) {
+    constexpr unsigned NG = 8;
+    while (d < NG) {
+        const unsigned g = (g0 + d) % NG;
+        const unsigned lo = (unsigned)((unsigned long long)nitems * g / NG);
+        const unsigned hi = (unsigned)((unsigned long long)nitems * (g + 1) / NG);
+        const unsigned c = atomicAdd(&wh->win_next[g], 1u);
+        if (lo + c < hi) return lo + c;
+        ++d;
     }
+    return WIN_NONE;
+}
+
+// Numeric phase of the heavy rows, one column window at a time by a
+// persistent grid (one block per CU slot).  A window's output columns are
+// marked first (one bit per column in LDS), their ranks are the exclusive
+// prefix of the bit counts, and the products are then added straight into a
+// dense array of values indexed by rank: no hashing, no probing, and the
+// window leaves in ascending column order.  The slice of B row k inside the
+// window is two loads from k's chunk index, or the whole row (filtered by
+// column) when the row is short.  For a row of at most 1024 entries of A each
+// thread holds one a_ik and its slice; the next window's item, a_ik and slice
+// are loaded in stages between the current window's passes, so that their
+// latency hides behind loads the window waits for anyway.  Output stores are
+// left in flight (a block barrier does not wait for stores).
+template <typename V>
+__global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__ items, unsigned nitems,
+                                                     const int32_t *__restrict__ cA,
+                                                     const V *__restrict__ vA,
+                                                     const int32_t *__restrict__ rB,
+                                                     const int32_t *__restrict__ long_id,
+                                                     const int32_t *__restrict__ idx, int nchunks,
+                                                     const int32_t *__restrict__ bc,
+                                                     const V *__restrict__ bv,
+                                                     int32_t *__restrict__ cC, V *__restrict__ vC,
+                                                     WsHdr *wh) {
+    constexpr int G = 1024;
+    __shared__ __align__(16) unsigned long long buf[RANK_BUDGET];   // words, then values
+    __shared__ SegLds<G, true, V> sg;
+    __shared__ unsigned s_claim[2];
+    const int tid = threadIdx.x;
     const int nch1 = nchunks + 1;
-    uint32_t *w32 = reinterpret_cast<uint32_t *>(buf);   // word w: bits w32[2w], rank prefix w32[2w+1]
-    {
-        const int ch_lo = it.ch_lo, ch_hi = it.ch_hi, count = it.count;
-        const int nwords = (ch_hi - ch_lo) * WORDS_PER_CHUNK;
+    const unsigned g0 = blockIdx.x % 8;
+    unsigned gd = 0;                     // thread 0: groups done
+    bool bad = false;
+
+    // the slice of B row k inside chunks [ch_lo, ch_hi)
+    auto slice_of = [&](int r0, int r1, int li, int ch_lo, int ch_hi, int &lo, int &hi) {
+        if (li >= 0) {
+            const int32_t *ix = idx + (size_t)li * nch1;
+            lo = r0 + ix[ch_lo];
+            hi = r0 + ix[ch_hi];
+        } else {
+            lo = r0;
+            hi = r1;
+        }
+    };
+
+    if (tid == 0) s_claim[0] = win_claim(wh, nitems, g0, gd);
+    __syncthreads();
+    unsigned cur = __builtin_amdgcn_readfirstlane(s_claim[0]);
+    int par = 0;
+    WinItem it{};
+    int lo = 0, hi = 0;
+    V a = V(0);
+    if (cur != WIN_NONE) {
+        it = items[cur];
+        if (it.a1 - it.a0 <= G && it.a0 + tid < it.a1) {
+            const int k = cA[it.a0 + tid];
+            a = vA[it.a0 + tid];
+            slice_of(rB[k], rB[k + 1], long_id[k], it.ch_lo, it.ch_hi, lo, hi);
+        }
+    }
+    while (cur != WIN_NONE) {
+        if (tid == 0) s_claim[par ^ 1] = win_claim(wh, nitems, g0, gd);
+        const bool resident = it.a1 - it.a0 <= G;
+        const int ch_lo = it.ch_lo, count = it.count;
+        const int nwords = (it.ch_hi - ch_lo) * WORDS_PER_CHUNK;
         const uint32_t span = (uint32_t)nwords * 32u;
         const int c0 = ch_lo << CHUNK_SHIFT;
+        uint32_t *w32 = reinterpret_cast<uint32_t *>(buf);   // word w: bits w32[2w], rank prefix w32[2w+1]
         V *vals = reinterpret_cast<V *>(buf + nwords);
         for (int i = tid; i < nwords; i += G) buf[i] = 0ull;
         for (int i = tid; i < count; i += G) vals[i] = V(0);
         __syncthreads();
-        auto slice = [&](int k, int &lo, int &hi) {
-            const int b0 = rB[k];
-            const int l = long_id[k];
-            if (l >= 0) {
-                const int32_t *ix = idx + (size_t)l * nch1;
-                lo = b0 + ix[ch_lo];
-                hi = b0 + ix[ch_hi];
-            } else {
-                lo = b0;
-                hi = rB[k + 1];
+
+        // next window, stage 1: its item and this thread's a_ik
+        const unsigned nxt = __builtin_amdgcn_readfirstlane(s_claim[par ^ 1]);
+        WinItem nit{};
+        int nk = -1;
+        V na = V(0);
+        if (nxt != WIN_NONE) {
+            nit = items[nxt];
+            if (nit.a1 - nit.a0 <= G && nit.a0 + tid < nit.a1) {
+                nk = cA[nit.a0 + tid];
+                na = vA[nit.a0 + tid];
             }
-        };
-        int lo = r0, hi = r1;
-        if (resident && li >= 0) {
-            const int32_t *ix = idx + (size_t)li * nch1;
-            lo = r0 + ix[ch_lo];
-            hi = r0 + ix[ch_hi];
         }
+
+        auto slice = [&](int k, int &l, int &h) {
+            slice_of(rB[k], rB[k + 1], long_id[k], it.ch_lo, it.ch_hi, l, h);
+        };
         // pass 1: occupancy bits
         auto mark = [&](const int (&q)[U_RANK1], const bool (&ok)[U_RANK1], const V (&)[U_RANK1]) {
             int col[U_RANK1];
@@ -622,8 +673,17 @@ __device__ __forceinline__ void num_window_item(const WinItem it, const int32_t 
             }
         };
         if (resident) enum_chunk<G, U_RANK1, false, V>(lo, hi - lo, V(0), sg, mark);
-        else enum_row<G, U_RANK1, false, V>(a0, a1, cA, nullptr, sg, slice, mark);
+        else enum_row<G, U_RANK1, false, V>(it.a0, it.a1, cA, nullptr, sg, slice, mark);
         __syncthreads();
+
+        // next window, stage 2: row pointers of B row k
+        int nr0 = 0, nr1 = 0, nli = -1;
+        if (nk >= 0) {
+            nr0 = rB[nk];
+            nr1 = rB[nk + 1];
+            nli = long_id[nk];
+        }
+
         // ranks: exclusive prefix of the bit counts, per word
         {
             const int S = (nwords + G - 1) / G;
@@ -641,6 +701,11 @@ __device__ __forceinline__ void num_window_item(const WinItem it, const int32_t 
             if (total != count) bad = true;
         }
         __syncthreads();
+
+        // next window, stage 3: the slice of B row k inside the next window
+        int nlo = 0, nhi = 0;
+        if (nk >= 0) slice_of(nr0, nr1, nli, nit.ch_lo, nit.ch_hi, nlo, nhi);
+
         // pass 2: values added at their rank
         auto add = [&](const int (&q)[U_RANK2], const bool (&ok)[U_RANK2], const V (&av)[U_RANK2]) {
             int col[U_RANK2];
@@ -662,8 +727,9 @@ __device__ __forceinline__ void num_window_item(const WinItem it, const int32_t 
             }
         };
         if (resident) enum_chunk<G, U_RANK2, true, V>(lo, hi - lo, a, sg, add);
-        else enum_row<G, U_RANK2, true, V>(a0, a1, cA, vA, sg, slice, add);
+        else enum_row<G, U_RANK2, true, V>(it.a0, it.a1, cA, vA, sg, slice, add);
         __syncthreads();
+
         // columns staged in rank (= ascending column) order, then written out
         // together with the values in consecutive runs
         int32_t *stage = reinterpret_cast<int32_t *>(buf + nwords + count);
@@ -683,47 +749,13 @@ __device__ __forceinline__ void num_window_item(const WinItem it, const int32_t 
             __builtin_nontemporal_store(vals[r], &vC[it.out_pos + r]);
         }
         __syncthreads();
-    }
-}
 
-
-// Numeric phase of the heavy rows: a persistent grid (one block per CU slot)
-// takes windows one after another.  Windows are sorted by first chunk; they
-// are split into eight contiguous ranges, one per group of blocks
-// blockIdx % 8 (workgroups are dealt round-robin over the XCDs, so a group is
-// one XCD and the blocks sharing an L2 read the same column slices of B);
-// a group claims its range's windows in order with an atomic counter and,
-// once done, helps the other groups.
-template <typename V>
-__global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__ items, unsigned nitems,
-                                                     const int32_t *__restrict__ rA,
-                                                     const int32_t *__restrict__ cA,
-                                                     const V *__restrict__ vA,
-                                                     const int32_t *__restrict__ rB,
-                                                     const int32_t *__restrict__ long_id,
-                                                     const int32_t *__restrict__ idx, int nchunks,
-                                                     const int32_t *__restrict__ bc,
-                                                     const V *__restrict__ bv,
-                                                     int32_t *__restrict__ cC, V *__restrict__ vC,
-                                                     WsHdr *wh) {
-    constexpr unsigned NG = 8;
-    __shared__ __align__(16) unsigned long long buf[RANK_BUDGET];   // words, then values
-    __shared__ SegLds<1024, true, V> sg;
-    __shared__ unsigned s_claim;
-    bool bad = false;
-    const unsigned g0 = blockIdx.x % NG;
-    for (unsigned d = 0; d < NG; ++d) {
-        const unsigned g = (g0 + d) % NG;
-        const unsigned lo = (unsigned)((unsigned long long)nitems * g / NG);
-        const unsigned hi = (unsigned)((unsigned long long)nitems * (g + 1) / NG);
-        for (;;) {
-            if (threadIdx.x == 0) s_claim = atomicAdd(&wh->win_next[g], 1u);
-            __syncthreads();
-            const unsigned i = lo + s_claim;
-            __syncthreads();                       // everyone has read s_claim
-            if (i >= hi) break;                    // uniform over the block
-            num_window_item<V>(items[i], rA, cA, vA, rB, long_id, idx, nchunks, bc, bv, cC, vC, buf, sg, bad);
-        }
+        cur = nxt;
+        it = nit;
+        lo = nlo;
+        hi = nhi;
+        a = na;
+        par ^= 1;
     }
     if (bad) atomicOr(&wh->err, ERR_COUNT);
 }
@@ -891,14 +923,15 @@ hipError_t launch_count_long_b(const CsrDev &B, PlanHdr *hdr, hipStream_t s) {
 }
 
 hipError_t launch_windows(unsigned nheavy_max, const HeavyRow *heavy, int nchunks, const uint32_t *chunk_cnt,
-                          const int64_t *rpts_C, uint32_t *whist, uint32_t *wcur, WinItem *items, unsigned cap,
-                          WsHdr *wh, hipStream_t s) {
+                          const int64_t *rpts_C, const int32_t *rA, uint32_t *whist, uint32_t *wcur, WinItem *items,
+                          unsigned cap, WsHdr *wh, hipStream_t s) {
     if (nheavy_max == 0) return hipSuccess;
     hipError_t e = hipMemsetAsync(whist, 0, sizeof(uint32_t) * 2 * (size_t)nchunks, s);   // whist and wcur
     if (e != hipSuccess) return e;
     k_win_count<<<grid1(nheavy_max, 256), 256, 0, s>>>(heavy, nchunks, chunk_cnt, whist, wh);
     k_win_scan<<<1, 1024, 0, s>>>(whist, nchunks, cap, wh);
-    k_win_emit<<<grid1(nheavy_max, 256), 256, 0, s>>>(heavy, nchunks, chunk_cnt, rpts_C, whist, wcur, items, cap, wh);
+    k_win_emit<<<grid1(nheavy_max, 256), 256, 0, s>>>(heavy, nchunks, chunk_cnt, rpts_C, rA, whist, wcur, items, cap,
+                                                       wh);
     return hipGetLastError();
 }
 
@@ -988,14 +1021,13 @@ hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, c
     if (dtype == 0) {
         static const int occ = blocks_per_cu(k_num_window<double>, 1024);
         const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
-        k_num_window<double><<<grid, 1024, 0, s>>>(items, nitems, A.rpts, A.cols, (const double *)A.vals, B.rpts,
-                                                   long_id, idx, nchunks, bc, (const double *)bv, cC, (double *)vC,
-                                                   wh);
+        k_num_window<double><<<grid, 1024, 0, s>>>(items, nitems, A.cols, (const double *)A.vals, B.rpts, long_id,
+                                                   idx, nchunks, bc, (const double *)bv, cC, (double *)vC, wh);
     } else {
         static const int occ = blocks_per_cu(k_num_window<unsigned long long>, 1024);
         const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
         k_num_window<unsigned long long><<<grid, 1024, 0, s>>>(
-            items, nitems, A.rpts, A.cols, (const unsigned long long *)A.vals, B.rpts, long_id, idx, nchunks, bc,
+            items, nitems, A.cols, (const unsigned long long *)A.vals, B.rpts, long_id, idx, nchunks, bc,
             (const unsigned long long *)bv, cC, (unsigned long long *)vC, wh);
     }
     return hipGetLastError();

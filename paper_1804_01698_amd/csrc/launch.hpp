@@ -37,8 +37,8 @@ hipError_t launch_num_hist(int m, const int32_t *nnz_row, const uint32_t *flop, 
                            const int32_t *slot_of, HeavyRow *heavy, WsHdr *wh, const BinLimits &L, hipStream_t s);
 hipError_t launch_count_long_b(const CsrDev &B, PlanHdr *hdr, hipStream_t s);
 hipError_t launch_windows(unsigned nheavy_max, const HeavyRow *heavy, int nchunks, const uint32_t *chunk_cnt,
-                          const int64_t *rpts_C, uint32_t *whist, uint32_t *wcur, WinItem *items, unsigned cap,
-                          WsHdr *wh, hipStream_t s);
+                          const int64_t *rpts_C, const int32_t *rA, uint32_t *whist, uint32_t *wcur, WinItem *items,
+                          unsigned cap, WsHdr *wh, hipStream_t s);
 hipError_t launch_bucket(const CsrDev &B, int32_t *bc, int32_t *bperm, int32_t *long_id, int32_t *long_list,
                          int32_t *idx, int nchunks, WsHdr *wh, hipStream_t s);
 hipError_t launch_gather_vals(int dtype, int64_t n, const int32_t *bperm, const void *vB, void *bv, hipStream_t s);
