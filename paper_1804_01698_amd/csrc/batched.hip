@@ -229,9 +229,10 @@ __global__ __launch_bounds__(G) void k_bat_hash(const BatchDesc *__restrict__ d,
                 V xv[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    col[u] = 0;
-                    xv[u] = V(0);
-                    if (ok[u]) { col[u] = q.cB[qq[u]]; xv[u] = av[u] * vB[qq[u]]; }
+                    const int c = q.cB[qq[u]];             // qq is always a valid index
+                    const V b = vB[qq[u]];
+                    col[u] = ok[u] ? c : 0;
+                    xv[u] = ok[u] ? av[u] * b : V(0);
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)

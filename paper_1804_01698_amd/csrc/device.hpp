@@ -215,7 +215,9 @@ struct SegLds {
 
 // One chunk: this thread's entry has slice [lo, lo+len) and multiplier a.
 // act(q[U], ok[U], a[U]) processes up to U products per lane: B index q,
-// multiplier a (numeric phase), ok = valid.
+// multiplier a (numeric phase), ok = valid.  q is a valid B index even where
+// ok is false (the first entry of some segment), so act may load at q
+// unconditionally and discard the value.
 template <int G, int U, bool NUM, typename V, bool SNUM, class ActF>
 __device__ __forceinline__ void enum_chunk(int lo, int len, V a, SegLds<G, SNUM, V> &sg, ActF act) {
     static_assert(SNUM || !NUM, "numeric enumeration needs room for the multipliers");
@@ -262,37 +264,33 @@ __device__ __forceinline__ void enum_chunk(int lo, int len, V a, SegLds<G, SNUM,
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     ok[u] = pb + WAVE * u + ln <= last;
-                    q[u] = base + WAVE * u;
+                    q[u] = ok[u] ? base + WAVE * u : sg.lo[e];
                     av[u] = a1;
                 }
             } else {
-                int ea[U], eb[U];
+                // each lane's U products: last segment with off <= p, found by a
+                // branch-free search over power-of-two strides from e (off[e] <=
+                // every p of the batch), clamped at eh
+                int pos[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    ea[u] = e;
-                    eb[u] = eh;
-                }
+                for (int u = 0; u < U; ++u) pos[u] = e;
                 const int r = eh - e;
-                const int steps = 32 - __clz(r);
-                for (int st = 0; st < steps; ++st) {
+                for (int step = r > 0 ? 1 << (31 - __clz(r)) : 0; step > 0; step >>= 1) {
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        if (ea[u] < eb[u]) {
-                            const int mid = (ea[u] + eb[u] + 1) >> 1;
-                            if (sg.off[mid] <= pb + WAVE * u + ln) ea[u] = mid; else eb[u] = mid - 1;
-                        }
+                        const int t = min(pos[u] + step, eh);
+                        pos[u] = sg.off[t] <= pb + WAVE * u + ln ? t : pos[u];
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int p = pb + WAVE * u + ln;
                     ok[u] = p <= last;
-                    q[u] = 0;
+                    // lanes past the range point at their segment's first entry
+                    // (a valid index) so that loads need no branch
+                    q[u] = sg.lo[pos[u]] + (ok[u] ? p - sg.off[pos[u]] : 0);
                     av[u] = V(0);
-                    if (ok[u]) {
-                        q[u] = sg.lo[ea[u]] + (p - sg.off[ea[u]]);
-                        if constexpr (NUM) av[u] = sg.a[ea[u]];
-                    }
+                    if constexpr (NUM) av[u] = sg.a[pos[u]];
                 }
             }
             act(q, ok, av);

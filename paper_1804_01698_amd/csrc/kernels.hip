@@ -213,7 +213,10 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
         [&](const int (&q)[U], const bool (&ok)[U], const double (&)[U]) {
             int col[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) col[u] = ok[u] ? cB[q[u]] : 0;
+            for (int u = 0; u < U; ++u) {
+                const int c = cB[q[u]];                   // q is always a valid index
+                col[u] = ok[u] ? c : 0;
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hmul);
@@ -265,7 +268,10 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
             [&](const int (&q)[U_SEG], const bool (&ok)[U_SEG], const double (&)[U_SEG]) {
                 int col[U_SEG];
 #pragma unroll
-                for (int u = 0; u < U_SEG; ++u) col[u] = ok[u] ? cB[q[u]] : -1;
+                for (int u = 0; u < U_SEG; ++u) {
+                    const int c = cB[q[u]];               // q is always a valid index
+                    col[u] = ok[u] ? c : -1;
+                }
 #pragma unroll
                 for (int u = 0; u < U_SEG; ++u) {
                     const uint32_t off = (uint32_t)((int64_t)col[u] - c0);
@@ -534,9 +540,10 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
             V x[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                col[u] = 0;
-                x[u] = V(0);
-                if (ok[u]) { col[u] = cB[q[u]]; x[u] = av[u] * vB[q[u]]; }
+                const int c = cB[q[u]];                   // q is always a valid index
+                const V b = vB[q[u]];
+                col[u] = ok[u] ? c : 0;
+                x[u] = ok[u] ? av[u] * b : V(0);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -665,7 +672,10 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         auto mark = [&](const int (&q)[U_RANK1], const bool (&ok)[U_RANK1], const V (&)[U_RANK1]) {
             int col[U_RANK1];
 #pragma unroll
-            for (int u = 0; u < U_RANK1; ++u) col[u] = ok[u] ? bc[q[u]] : c0 - 1;
+            for (int u = 0; u < U_RANK1; ++u) {
+                const int c = bc[q[u]];                   // q is always a valid index
+                col[u] = ok[u] ? c : c0 - 1;
+            }
 #pragma unroll
             for (int u = 0; u < U_RANK1; ++u) {
                 const uint32_t off = (uint32_t)(col[u] - c0);
@@ -712,9 +722,10 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
             V x[U_RANK2];
 #pragma unroll
             for (int u = 0; u < U_RANK2; ++u) {
-                col[u] = c0 - 1;
-                x[u] = V(0);
-                if (ok[u]) { col[u] = bc[q[u]]; x[u] = av[u] * bv[q[u]]; }
+                const int c = bc[q[u]];                   // q is always a valid index
+                const V b = bv[q[u]];
+                col[u] = ok[u] ? c : c0 - 1;
+                x[u] = ok[u] ? av[u] * b : V(0);
             }
 #pragma unroll
             for (int u = 0; u < U_RANK2; ++u) {
