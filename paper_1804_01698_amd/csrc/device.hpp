@@ -211,6 +211,7 @@ struct SegLds {
     int off[G];
     V a[NUM ? G : 1];
     int wsum[G / WAVE + 1];
+    uint2 starts[G / WAVE][32];   // per wave: segment-start bits of a batch, prefix counts
 };
 
 // One chunk: this thread's entry has slice [lo, lo+len) and multiplier a.
@@ -268,30 +269,42 @@ __device__ __forceinline__ void enum_chunk(int lo, int len, V a, SegLds<G, SNUM,
                     av[u] = a1;
                 }
             } else {
-                // each lane's U products: last segment with off <= p, found by a
-                // branch-free search over power-of-two strides from e (off[e] <=
-                // every p of the batch), clamped at eh
-                int pos[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) pos[u] = e;
-                const int r = eh - e;
-                for (int step = r > 0 ? 1 << (31 - __clz(r)) : 0; step > 0; step >>= 1) {
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int t = min(pos[u] + step, eh);
-                        pos[u] = sg.off[t] <= pb + WAVE * u + ln ? t : pos[u];
-                    }
+                // segment of each product of the batch: the wave marks where
+                // the segments e+1..eh start inside [pb, pb + 64U) in an LDS
+                // bitmap with per-word prefix counts; product p then lies in
+                // segment e + (number of starts at or before p).
+                static_assert(U * WAVE <= 32 * 32, "batch larger than the start bitmap");
+                constexpr int NWD = (U * WAVE + 31) / 32;
+                uint2 *sb = sg.starts[w];
+                if (ln < NWD) sb[ln].x = 0u;
+                wave_sync();
+                for (int sidx = e + 1 + ln; sidx <= eh; sidx += WAVE) {
+                    const int rel = sg.off[sidx] - pb;
+                    atomicOr(&sb[rel >> 5].x, 1u << (rel & 31));
                 }
+                wave_sync();
+                {
+                    const uint32_t bits = ln < NWD ? sb[ln].x : 0u;
+                    const int c = __popc(bits);
+                    const int incl = wave_incl_scan<int>(c);
+                    if (ln < NWD) sb[ln].y = (uint32_t)(incl - c);
+                }
+                wave_sync();
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int p = pb + WAVE * u + ln;
+                    const int rel = WAVE * u + ln;
+                    const int p = pb + rel;
+                    const uint2 bw = sb[rel >> 5];
+                    const uint32_t upto = (uint32_t)((2ull << (rel & 31)) - 1ull);
+                    const int seg = e + (int)bw.y + __popc(bw.x & upto);
                     ok[u] = p <= last;
                     // lanes past the range point at their segment's first entry
                     // (a valid index) so that loads need no branch
-                    q[u] = sg.lo[pos[u]] + (ok[u] ? p - sg.off[pos[u]] : 0);
+                    q[u] = sg.lo[seg] + (ok[u] ? p - sg.off[seg] : 0);
                     av[u] = V(0);
-                    if constexpr (NUM) av[u] = sg.a[pos[u]];
+                    if constexpr (NUM) av[u] = sg.a[seg];
                 }
+                wave_sync();        // the bitmap is reused by the next batch
             }
             act(q, ok, av);
             e = eh;

@@ -28,7 +28,7 @@ namespace spg {
 // Products per lane per batch (memory-level parallelism), by kernel family.
 constexpr int U_SEG = 16;
 constexpr int U_RANK1 = 16;
-constexpr int U_RANK2 = 16;
+constexpr int U_RANK2 = 8;
 
 // ----------------------------------------------------------------------- validate
 
