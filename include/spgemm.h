@@ -56,8 +56,14 @@ enum {
     SPGEMM_VALIDATE = 1u << 1, /* check A and B structure on the device at plan time
                                   (row pointers non-decreasing from 0 to nnz, column
                                   ids in range); failure gives SPGEMM_ERR_INVALID_CSR */
-    SPGEMM_TIMING = 1u << 2    /* record HIP events around every kernel launch from
+    SPGEMM_TIMING = 1u << 2,   /* record HIP events around every kernel launch from
                                   the plan on (see spgemm_plan_kernel_times)        */
+    SPGEMM_LOW_MEMORY = 1u << 3 /* do not keep the symbolic bitmaps of rows whose
+                                  key bound exceeds 8448 for the numeric phase: a
+                                  smaller workspace (by nrows_in_that_bin *
+                                  ceil(ncols/4096) * 512 bytes) and a slower numeric
+                                  phase.  Without it they are kept when they take
+                                  at most 64 GiB.                                  */
 };
 
 /* Status codes. */

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libspgemm.so")
 
 F64, I64 = 0, 1
-SORTED, VALIDATE, TIMING = 1, 2, 4
+SORTED, VALIDATE, TIMING, LOW_MEMORY = 1, 2, 4, 8
 
 
 def lib_path() -> str:
@@ -189,7 +189,7 @@ class Plan:
 
     def __init__(self, As: Sequence[DeviceCSR], Bs: Sequence[DeviceCSR], sorted_output: bool = True,
                  dtype: Optional[int] = None, validate: bool = False, stream=None, timing: bool = False,
-                 defer_workspace: bool = False, config: Optional[dict] = None):
+                 defer_workspace: bool = False, config: Optional[dict] = None, low_memory: bool = False):
         if len(As) != len(Bs) or not As:
             raise ValueError("need equal, non-empty lists of operands")
         self.As, self.Bs = list(As), list(Bs)
@@ -204,7 +204,8 @@ class Plan:
         nbytes = _lib.spgemm_plan_scratch_bytes(self.n, self._ca)
         self.plan_scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
         ws = ctypes.c_size_t(0)
-        flags = (SORTED if self.sorted else 0) | (VALIDATE if validate else 0) | (TIMING if timing else 0)
+        flags = ((SORTED if self.sorted else 0) | (VALIDATE if validate else 0) | (TIMING if timing else 0)
+                 | (LOW_MEMORY if low_memory else 0))
         cs = _config_struct(config)
         st = _lib.spgemm_plan(ctypes.byref(self._h), self.n, self._ca, self._cb, self.dtype, flags,
                               ctypes.c_void_p(self.plan_scratch.data_ptr()), _stream_handle(stream),

@@ -58,7 +58,8 @@ struct Prod {
     size_t ws_base = 0, ws_bytes = 0;
     size_t o_hdr = 0, o_perm_sym = 0, o_perm_num = 0, o_nnz = 0, o_bsum = 0;
     size_t o_chunk = 0, o_heavy = 0, o_items = 0, o_bc = 0, o_bv = 0, o_long = 0;
-    size_t o_whist = 0, o_long_id = 0, o_idx = 0, o_slot = 0, o_bperm = 0;
+    size_t o_whist = 0, o_long_id = 0, o_idx = 0, o_slot = 0, o_bperm = 0, o_bmap = 0;
+    bool store_bm = false;    // symbolic bitmaps kept for the numeric windows
     // after symbolic
     char *ws = nullptr;
     WsHdr *wh = nullptr;
@@ -187,7 +188,8 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     *out = nullptr;
     if (nprod <= 0 || !A || !B || !workspace_bytes) return SPGEMM_ERR_INVALID_ARG;
     if (dtype != SPGEMM_F64 && dtype != SPGEMM_I64) return SPGEMM_ERR_INVALID_ARG;
-    if (flags & ~(unsigned)(SPGEMM_SORTED | SPGEMM_VALIDATE | SPGEMM_TIMING)) return SPGEMM_ERR_INVALID_ARG;
+    if (flags & ~(unsigned)(SPGEMM_SORTED | SPGEMM_VALIDATE | SPGEMM_TIMING | SPGEMM_LOW_MEMORY))
+        return SPGEMM_ERR_INVALID_ARG;
     for (int p = 0; p < nprod; ++p) {
         if (!csr_ok(A[p]) || !csr_ok(B[p])) return SPGEMM_ERR_INVALID_ARG;
         if (A[p].ncols != B[p].nrows) return SPGEMM_ERR_SHAPE;
@@ -292,6 +294,9 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
             q.items_cap = (unsigned)cap;
 
             q.o_chunk = o; o += align_up(4 * (size_t)q.nbm * (size_t)q.nchunks);
+            const unsigned long long bm_bytes = 4ull * WORDS_PER_CHUNK * (unsigned long long)q.nbm * q.nchunks;
+            q.store_bm = !(flags & SPGEMM_LOW_MEMORY) && bm_bytes <= BM_STORE_MAX;
+            if (q.store_bm) { q.o_bmap = o; o += align_up((size_t)bm_bytes); }
             q.o_heavy = o; o += align_up(sizeof(HeavyRow) * (size_t)q.nbm);
             q.o_items = o; o += align_up(sizeof(WinItem) * (size_t)q.items_cap);
             q.o_whist = o; o += align_up(sizeof(uint32_t) * 2 * (size_t)q.nchunks);
@@ -353,7 +358,8 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
                 HIPCK(timed(pl, "sym_bitmap", rows_bytes + 4.0 * nr * q.nchunks,
                             [&] {
                                 return launch_sym_segments(nr, perm, off.v[b], q.A, q.B, q.nchunks,
-                                                           q.at<uint32_t>(q.o_chunk), nnz, s);
+                                                           q.at<uint32_t>(q.o_chunk), nnz,
+                                                           q.store_bm ? q.at<uint32_t>(q.o_bmap) : nullptr, s);
                             }),
                       "sym_bitmap");
             } else {
@@ -461,7 +467,8 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
                             return launch_num_window(pl->dtype, q.hw.n_items, q.at<WinItem>(q.o_items), q.A, q.B,
                                                      q.at<int32_t>(q.o_long_id), q.at<int32_t>(q.o_idx), q.nchunks,
                                                      q.at<int32_t>(q.o_bc), q.at<void>(q.o_bv), cols_C[p],
-                                                     vals_C[p], q.wh, pl->ncu, s);
+                                                     vals_C[p], q.store_bm ? q.at<uint32_t>(q.o_bmap) : nullptr,
+                                                     q.wh, pl->ncu, s);
                         }),
                   "num_window");
         }

@@ -150,7 +150,13 @@ struct WinItem {
     int32_t count;      // output entries in the window (from the symbolic bitmap)
     int64_t out_pos;    // absolute position in cols_C / vals_C
     int32_t a0, a1;     // the row's entries of A: [a0, a1)
+    int32_t slot;       // the row's index within the bitmap bin
+    int32_t pad;
 };
+
+// Stored symbolic bitmaps of the bitmap-bin rows (one bit per column of C,
+// whole chunks per row) are kept when they take at most this many bytes.
+constexpr unsigned long long BM_STORE_MAX = 64ull << 30;
 
 struct HeavyRow {
     int32_t row;

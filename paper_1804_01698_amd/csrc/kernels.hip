@@ -242,7 +242,8 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
                                                      const int32_t *__restrict__ rB,
                                                      const int32_t *__restrict__ cB, int64_t ncols,
                                                      int nchunks, uint32_t *__restrict__ chunk_cnt,
-                                                     int32_t *__restrict__ nnz_row) {
+                                                     int32_t *__restrict__ nnz_row,
+                                                     uint32_t *__restrict__ bmap) {
     constexpr int G = 1024;
     constexpr int NW = G / WAVE;
     constexpr int64_t WIN = (int64_t)NWORDS * 32;
@@ -281,6 +282,12 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
         __syncthreads();
         const int nch = (int)((wcols + CHUNK_COLS - 1) >> CHUNK_SHIFT);
         const int chunk0 = (int)(c0 >> CHUNK_SHIFT);
+        if (bmap) {
+            // the row's bits are kept for the numeric windows (whole chunks)
+            uint32_t *dst = bmap + ((size_t)slot * nchunks + chunk0) * WORDS_PER_CHUNK;
+            for (int i = tid; i < nch * WORDS_PER_CHUNK; i += G)
+                __builtin_nontemporal_store(i < nw ? bm[i] : 0u, &dst[i]);
+        }
         for (int c = w; c < nch; c += NW) {
             int cw = 0;
             for (int j = ln; j < WORDS_PER_CHUNK; j += WAVE) {
@@ -428,7 +435,7 @@ __global__ __launch_bounds__(256) void k_win_emit(const HeavyRow *__restrict__ h
     const int a0 = rA[hr.row], a1 = rA[hr.row + 1];
     for_each_window(cc, nchunks, [&](int lo, int hi, int cnt) {
         const unsigned at = wpos[lo] + atomicAdd(&wcur[lo], 1u);
-        if (at < cap) items[at] = WinItem{hr.row, lo, hi, cnt, pos, a0, a1};
+        if (at < cap) items[at] = WinItem{hr.row, lo, hi, cnt, pos, a0, a1, hr.slot, 0};
         pos += cnt;
     });
 }
@@ -586,7 +593,9 @@ __device__ __forceinline__ unsigned win_claim(WsHdr *wh, unsigned nitems, unsign
 // dense array of values indexed by rank: no hashing, no probing, and the
 // window leaves in ascending column order.  The slice of B row k inside the
 // window is two loads from k's chunk index, or the whole row (filtered by
-// column) when the row is short.  For a row of at most 1024 entries of A each
+// column) when the row is short.  When the symbolic phase kept the row's
+// bits, pass 1 is a copy of the window's words instead.  For a row of at most
+// 1024 entries of A each
 // thread holds one a_ik and its slice; the next window's item, a_ik and slice
 // are loaded in stages between the current window's passes, so that their
 // latency hides behind loads the window waits for anyway.  Output stores are
@@ -601,7 +610,7 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
                                                      const int32_t *__restrict__ bc,
                                                      const V *__restrict__ bv,
                                                      int32_t *__restrict__ cC, V *__restrict__ vC,
-                                                     WsHdr *wh) {
+                                                     const uint32_t *__restrict__ bmap, WsHdr *wh) {
     constexpr int G = 1024;
     __shared__ __align__(16) unsigned long long buf[RANK_BUDGET];   // words, then values
     __shared__ SegLds<G, true, V> sg;
@@ -648,7 +657,13 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         const int c0 = ch_lo << CHUNK_SHIFT;
         uint32_t *w32 = reinterpret_cast<uint32_t *>(buf);   // word w: bits w32[2w], rank prefix w32[2w+1]
         V *vals = reinterpret_cast<V *>(buf + nwords);
-        for (int i = tid; i < nwords; i += G) buf[i] = 0ull;
+        if (bmap) {
+            // the window's occupancy bits from the symbolic phase
+            const uint32_t *src = bmap + ((size_t)it.slot * nchunks + ch_lo) * WORDS_PER_CHUNK;
+            for (int i = tid; i < nwords; i += G) buf[i] = (unsigned long long)__builtin_nontemporal_load(&src[i]);
+        } else {
+            for (int i = tid; i < nwords; i += G) buf[i] = 0ull;
+        }
         for (int i = tid; i < count; i += G) vals[i] = V(0);
         __syncthreads();
 
@@ -682,8 +697,10 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
                 if (off < span) atomicOr(&w32[2 * (off >> 5)], 1u << (off & 31));
             }
         };
-        if (resident) enum_chunk<G, U_RANK1, false, V>(lo, hi - lo, V(0), sg, mark);
-        else enum_row<G, U_RANK1, false, V>(it.a0, it.a1, cA, nullptr, sg, slice, mark);
+        if (!bmap) {
+            if (resident) enum_chunk<G, U_RANK1, false, V>(lo, hi - lo, V(0), sg, mark);
+            else enum_row<G, U_RANK1, false, V>(it.a0, it.a1, cA, nullptr, sg, slice, mark);
+        }
         __syncthreads();
 
         // next window, stage 2: row pointers of B row k
@@ -896,18 +913,18 @@ hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t 
 }
 
 hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, hipStream_t s) {
+                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, hipStream_t s) {
     if (nbm == 0) return hipSuccess;
     const int64_t need = (B.ncols + 31) / 32;
     if (need <= BM_WORDS_SMALL)
         k_sym_bitmap<BM_WORDS_SMALL><<<nbm, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks,
-                                                          chunk_cnt, nnz_row);
+                                                          chunk_cnt, nnz_row, bmap);
     else if (need <= BM_WORDS_MID)
         k_sym_bitmap<BM_WORDS_MID><<<nbm, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks,
-                                                        chunk_cnt, nnz_row);
+                                                        chunk_cnt, nnz_row, bmap);
     else
         k_sym_bitmap<BM_WORDS_LARGE><<<nbm, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks,
-                                                          chunk_cnt, nnz_row);
+                                                          chunk_cnt, nnz_row, bmap);
     return hipGetLastError();
 }
 
@@ -1026,20 +1043,22 @@ static int blocks_per_cu(K kern, int G) {
 // Windows leave in ascending column order, so sorted and unsorted output share it.
 hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
                              const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
-                             const void *bv, int32_t *cC, void *vC, WsHdr *wh, int ncu, hipStream_t s) {
+                             const void *bv, int32_t *cC, void *vC, const uint32_t *bmap, WsHdr *wh, int ncu,
+                             hipStream_t s) {
     if (nitems == 0) return hipSuccess;
     k_zero_u32n<<<1, 64, 0, s>>>(wh->win_next, 8);
     if (dtype == 0) {
         static const int occ = blocks_per_cu(k_num_window<double>, 1024);
         const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
         k_num_window<double><<<grid, 1024, 0, s>>>(items, nitems, A.cols, (const double *)A.vals, B.rpts, long_id,
-                                                   idx, nchunks, bc, (const double *)bv, cC, (double *)vC, wh);
+                                                   idx, nchunks, bc, (const double *)bv, cC, (double *)vC, bmap,
+                                                   wh);
     } else {
         static const int occ = blocks_per_cu(k_num_window<unsigned long long>, 1024);
         const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
         k_num_window<unsigned long long><<<grid, 1024, 0, s>>>(
             items, nitems, A.cols, (const unsigned long long *)A.vals, B.rpts, long_id, idx, nchunks, bc,
-            (const unsigned long long *)bv, cC, (unsigned long long *)vC, wh);
+            (const unsigned long long *)bv, cC, (unsigned long long *)vC, bmap, wh);
     }
     return hipGetLastError();
 }

@@ -30,7 +30,7 @@ hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const
 hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
                           const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, hipStream_t s);
 hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, hipStream_t s);
+                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, hipStream_t s);
 hipError_t launch_scan(const int32_t *nnz_row, int m, long long *bsum, int64_t *rpts_C, WsHdr *wh,
                        hipStream_t s);
 hipError_t launch_num_hist(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
@@ -49,7 +49,8 @@ hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const
                           WsHdr *wh, uint32_t hmul, hipStream_t s);
 hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
                              const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
-                             const void *bv, int32_t *cC, void *vC, WsHdr *wh, int ncu, hipStream_t s);
+                             const void *bv, int32_t *cC, void *vC, const uint32_t *bmap, WsHdr *wh, int ncu,
+                             hipStream_t s);
 hipError_t launch_masked_sum(int64_t m, int64_t ncols, const int64_t *rC, const int32_t *cC, const int64_t *vC,
                              const CsrDev &M, int64_t *out, hipStream_t s);
 hipError_t launch_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t s);

@@ -104,14 +104,16 @@ def test_rmat_mid(sp, scale, sorted_output):
 
 
 @pytest.mark.parametrize("sorted_output", [True, False])
-def test_rmat16_full(sp, sorted_output):
-    """R-MAT scale 16 ef 16 A*A: every bin, bitmap symbolic and column windows."""
-    _note(f"case rmat16_full sorted={sorted_output}")
+@pytest.mark.parametrize("low_memory", [False, True])
+def test_rmat16_full(sp, sorted_output, low_memory):
+    """R-MAT scale 16 ef 16 A*A: every bin, bitmap symbolic and column windows
+    (with the symbolic bitmaps kept for the windows, and without)."""
+    _note(f"case rmat16_full sorted={sorted_output} low_memory={low_memory}")
     A = rmat(16, 16, 1)
     if not sorted_output:
         A = shuffle_within_rows(A, 3)
     dA = _dev(sp, A)
-    p = sp.Plan([dA], [dA], sorted_output=sorted_output)
+    p = sp.Plan([dA], [dA], sorted_output=sorted_output, low_memory=low_memory)
     p.symbolic()
     C = p.numeric()[0]
     st = p.stats(0)
@@ -142,9 +144,17 @@ def test_wide_columns_multipass_bitmap(sp):
     rp = np.zeros(len(rows) + 1, dtype=np.int64)
     np.cumsum([r.size for r in rows], out=rp[1:])
     A = with_values(CSR(len(rows), 3000, rp, np.concatenate(rows).astype(np.int32), None), 9, "f64")
+    import torch
+    dA, dB = _dev(sp, A), _dev(sp, B)
     for srt in (True, False):
-        C = _run(sp, A, B, srt)
-        assert_matches(C, oracle.spgemm(A, B, sorted_output=srt), srt)
+        for low in (False, True):
+            p = sp.Plan([dA], [dB], sorted_output=srt, low_memory=low)
+            p.symbolic()
+            C = p.numeric()[0]
+            torch.cuda.synchronize()
+            assert p.stats(0)["status"] == 0
+            p.close()
+            assert_matches(C, oracle.spgemm(A, B, sorted_output=srt), srt)
 
 
 def test_rectangular_tall_skinny_bfs(sp):
