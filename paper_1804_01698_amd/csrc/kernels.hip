@@ -573,18 +573,28 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
 // block takes its group's windows in order and then helps the other groups.
 constexpr unsigned WIN_NONE = 0xFFFFFFFFu;
 
-__device__ __forceinline__ unsigned win_claim(WsHdr *wh, unsigned nitems, unsigned g0, unsigned &d) {
+// Claims run one window ahead of their use: the block holds the raw counter
+// value of an issued claim (raw) and turns it into a window index only when
+// that window is next, so the atomic's latency is not waited for.
+__device__ __forceinline__ unsigned win_resolve(WsHdr *wh, unsigned nitems, unsigned g0, unsigned &d,
+                                                unsigned &raw) {
     constexpr unsigned NG = 8;
     while (d < NG) {
         const unsigned g = (g0 + d) % NG;
         const unsigned lo = (unsigned)((unsigned long long)nitems * g / NG);
         const unsigned hi = (unsigned)((unsigned long long)nitems * (g + 1) / NG);
-        const unsigned c = atomicAdd(&wh->win_next[g], 1u);
-        if (lo + c < hi) return lo + c;
-        ++d;
+        if (lo + raw < hi) return lo + raw;
+        if (++d < NG) raw = atomicAdd(&wh->win_next[(g0 + d) % NG], 1u);   // this group is done
     }
     return WIN_NONE;
 }
+
+__device__ __forceinline__ void win_issue(WsHdr *wh, unsigned g0, unsigned d, unsigned &raw) {
+    if (d < 8) raw = atomicAdd(&wh->win_next[(g0 + d) % 8], 1u);
+}
+
+// Words of a window's bitmap held in registers ahead of its turn.
+constexpr int WIN_PRE_WORDS = 3;
 
 // Numeric phase of the heavy rows, one column window at a time by a
 // persistent grid (one block per CU slot).  A window's output columns are
@@ -619,6 +629,7 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
     const int nch1 = nchunks + 1;
     const unsigned g0 = blockIdx.x % 8;
     unsigned gd = 0;                     // thread 0: groups done
+    unsigned raw = 0;                    // thread 0: raw value of the claim in flight
     bool bad = false;
 
     // the slice of B row k inside chunks [ch_lo, ch_hi)
@@ -633,9 +644,15 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         }
     };
 
-    if (tid == 0) s_claim[0] = win_claim(wh, nitems, g0, gd);
+    if (tid == 0) {
+        win_issue(wh, g0, gd, raw);
+        s_claim[0] = win_resolve(wh, nitems, g0, gd, raw);
+        win_issue(wh, g0, gd, raw);
+    }
     __syncthreads();
     unsigned cur = __builtin_amdgcn_readfirstlane(s_claim[0]);
+    uint32_t pre[WIN_PRE_WORDS];         // the current window's bitmap words, when preloaded
+    bool have_pre = false;
     int par = 0;
     WinItem it{};
     int lo = 0, hi = 0;
@@ -649,7 +666,10 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         }
     }
     while (cur != WIN_NONE) {
-        if (tid == 0) s_claim[par ^ 1] = win_claim(wh, nitems, g0, gd);
+        if (tid == 0) {
+            s_claim[par ^ 1] = win_resolve(wh, nitems, g0, gd, raw);
+            win_issue(wh, g0, gd, raw);
+        }
         const bool resident = it.a1 - it.a0 <= G;
         const int ch_lo = it.ch_lo, count = it.count;
         const int nwords = (it.ch_hi - ch_lo) * WORDS_PER_CHUNK;
@@ -657,7 +677,11 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         const int c0 = ch_lo << CHUNK_SHIFT;
         uint32_t *w32 = reinterpret_cast<uint32_t *>(buf);   // word w: bits w32[2w], rank prefix w32[2w+1]
         V *vals = reinterpret_cast<V *>(buf + nwords);
-        if (bmap) {
+        if (bmap && have_pre) {
+#pragma unroll
+            for (int k = 0; k < WIN_PRE_WORDS; ++k)
+                if (tid + k * G < nwords) buf[tid + k * G] = (unsigned long long)pre[k];
+        } else if (bmap) {
             // the window's occupancy bits from the symbolic phase
             const uint32_t *src = bmap + ((size_t)it.slot * nchunks + ch_lo) * WORDS_PER_CHUNK;
             for (int i = tid; i < nwords; i += G) buf[i] = (unsigned long long)__builtin_nontemporal_load(&src[i]);
@@ -729,9 +753,21 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         }
         __syncthreads();
 
-        // next window, stage 3: the slice of B row k inside the next window
+        // next window, stage 3: the slice of B row k inside the next window, and
+        // its bitmap words when they fit the registers
         int nlo = 0, nhi = 0;
         if (nk >= 0) slice_of(nr0, nr1, nli, nit.ch_lo, nit.ch_hi, nlo, nhi);
+        const int nnw = (nit.ch_hi - nit.ch_lo) * WORDS_PER_CHUNK;
+        const bool npre = bmap && nxt != WIN_NONE && nnw <= WIN_PRE_WORDS * G;
+        uint32_t npw[WIN_PRE_WORDS];
+#pragma unroll
+        for (int k = 0; k < WIN_PRE_WORDS; ++k) npw[k] = 0u;
+        if (npre) {
+            const uint32_t *src = bmap + ((size_t)nit.slot * nchunks + nit.ch_lo) * WORDS_PER_CHUNK;
+#pragma unroll
+            for (int k = 0; k < WIN_PRE_WORDS; ++k)
+                if (tid + k * G < nnw) npw[k] = __builtin_nontemporal_load(&src[tid + k * G]);
+        }
 
         // pass 2: values added at their rank
         auto add = [&](const int (&q)[U_RANK2], const bool (&ok)[U_RANK2], const V (&av)[U_RANK2]) {
@@ -783,6 +819,9 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         lo = nlo;
         hi = nhi;
         a = na;
+#pragma unroll
+        for (int k = 0; k < WIN_PRE_WORDS; ++k) pre[k] = npw[k];
+        have_pre = npre;
         par ^= 1;
     }
     if (bad) atomicOr(&wh->err, ERR_COUNT);
