@@ -52,42 +52,66 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nrows, int64_t ncols, 
 
 // ----------------------------------------------------------------------- row flop
 
-// 256 consecutive rows per block; the block's A entries are walked flat, each
-// lane locating its row by binary search over the block's row pointers.
+// Row flop in two steps.  First every entry a_ik of A gets the length of B
+// row k (a flat, fully parallel gather).  Then 256 consecutive rows per
+// block: a row of at most 64 entries is summed by its own thread (contiguous
+// reads); longer rows (the hub rows of skewed inputs) are summed by the whole
+// block in turn, so no block waits on a long chain of dependent loads.
+__global__ __launch_bounds__(256) void k_entry_deg(int64_t nnz, const int32_t *__restrict__ cA,
+                                                   const int32_t *__restrict__ rB, uint32_t *__restrict__ edeg) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nnz; e += stride) {
+        const int k = cA[e];
+        edeg[e] = (uint32_t)(rB[k + 1] - rB[k]);
+    }
+}
+
+constexpr int FLOP_SHORT_ROW = 64;
+
 __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restrict__ rA,
-                                                  const int32_t *__restrict__ cA,
-                                                  const int32_t *__restrict__ rB, int64_t ncolsB,
+                                                  const uint32_t *__restrict__ edeg, int64_t ncolsB,
                                                   uint32_t *__restrict__ flop_out, PlanHdr *hdr, BinLimits L) {
-    __shared__ int s_rp[257];
     __shared__ unsigned long long s_f[256];
+    __shared__ int s_long[256];
+    __shared__ int s_nlong;
     __shared__ unsigned long long s_rows[NSB], s_flop[NSB], s_nnza[NSB];
     __shared__ unsigned long long s_tot, s_max;
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * 256;
     const int nr = min(256, m - r0);
-    for (int t = tid; t <= nr; t += 256) s_rp[t] = rA[r0 + t];
-    s_f[tid] = 0;
     if (tid < NSB) { s_rows[tid] = 0; s_flop[tid] = 0; s_nnza[tid] = 0; }
-    if (tid == 0) { s_tot = 0; s_max = 0; }
+    if (tid == 0) { s_tot = 0; s_max = 0; s_nlong = 0; }
     __syncthreads();
-    const int p0 = s_rp[0], p1 = s_rp[nr];
-    for (int p = p0 + tid; p < p1; p += 256) {
-        int lo = 0, hi = nr;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_rp[mid] <= p) lo = mid; else hi = mid - 1;
+    int a0 = 0, a1 = 0;
+    unsigned long long f = 0;
+    if (tid < nr) {
+        a0 = rA[r0 + tid];
+        a1 = rA[r0 + tid + 1];
+        if (a1 - a0 <= FLOP_SHORT_ROW) {
+            for (int p = a0; p < a1; ++p) f += edeg[p];
+        } else {
+            s_long[atomicAdd(&s_nlong, 1)] = tid;
         }
-        const int k = cA[p];
-        atomicAdd(&s_f[lo], (unsigned long long)(rB[k + 1] - rB[k]));
+    }
+    s_f[tid] = f;
+    __syncthreads();
+    const int nlong = s_nlong;
+    for (int j = 0; j < nlong; ++j) {                  // uniform over the block
+        const int t = s_long[j];
+        const int b0 = rA[r0 + t], b1 = rA[r0 + t + 1];
+        unsigned long long g = 0;
+        for (int p = b0 + tid; p < b1; p += 256) g += edeg[p];
+        g = wave_sum_u64(g);
+        if ((tid & 63) == 0 && g) atomicAdd(&s_f[t], g);
     }
     __syncthreads();
     if (tid < nr) {
-        const unsigned long long f = s_f[tid];
+        f = s_f[tid];
         flop_out[r0 + tid] = f > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)f;
         const int b = sym_bin_l(f, ncolsB, L);
         atomicAdd(&s_rows[b], 1ull);
         atomicAdd(&s_flop[b], f);
-        atomicAdd(&s_nnza[b], (unsigned long long)(s_rp[tid + 1] - s_rp[tid]));
+        atomicAdd(&s_nnza[b], (unsigned long long)(a1 - a0));
         atomicAdd(&s_tot, f);
         atomicMax(&s_max, f);
     }
@@ -282,12 +306,6 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
         __syncthreads();
         const int nch = (int)((wcols + CHUNK_COLS - 1) >> CHUNK_SHIFT);
         const int chunk0 = (int)(c0 >> CHUNK_SHIFT);
-        if (bmap) {
-            // the row's bits are kept for the numeric windows (whole chunks)
-            uint32_t *dst = bmap + ((size_t)slot * nchunks + chunk0) * WORDS_PER_CHUNK;
-            for (int i = tid; i < nch * WORDS_PER_CHUNK; i += G)
-                __builtin_nontemporal_store(i < nw ? bm[i] : 0u, &dst[i]);
-        }
         for (int c = w; c < nch; c += NW) {
             int cw = 0;
             for (int j = ln; j < WORDS_PER_CHUNK; j += WAVE) {
@@ -299,6 +317,15 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
                 chunk_cnt[(size_t)slot * nchunks + chunk0 + c] = (uint32_t)cw;
                 atomicAdd(&s_total, cw);
             }
+        }
+        __syncthreads();
+        // the row's bits are kept for the numeric windows (whole chunks); a
+        // one-pass row that ends up with at most WIN_CAP entries takes a hash
+        // table instead and needs none
+        if (bmap && (npass > 1 || s_total > WIN_CAP)) {
+            uint32_t *dst = bmap + ((size_t)slot * nchunks + chunk0) * WORDS_PER_CHUNK;
+            for (int i = tid; i < nch * WORDS_PER_CHUNK; i += G)
+                __builtin_nontemporal_store(i < nw ? bm[i] : 0u, &dst[i]);
         }
         __syncthreads();
     }
@@ -369,40 +396,71 @@ __global__ __launch_bounds__(1024) void k_scan_down(const int32_t *__restrict__ 
 // and a half-word staging slot); empty chunks are not opened at a window
 // start.  The windows are laid out sorted by first chunk so that the blocks
 // running side by side read the same column slices of the shared B rows.
+// One wave per heavy row: the row's chunk counts are read 64 at a time
+// (coalesced) and the greedy split runs on wave-uniform state; f(lo, hi, cnt)
+// is called by every lane of the wave for every window.
 template <class F>
-__device__ __forceinline__ void for_each_window(const uint32_t *__restrict__ cc, int nchunks, F f) {
+__device__ __forceinline__ void wave_windows(const uint32_t *__restrict__ cc, int nchunks, F f) {
+    const int ln = threadIdx.x & 63;
     int units = 0, cnt = 0, start = 0;
-    for (int c = 0; c < nchunks; ++c) {
-        const int x = (int)cc[c];
-        if (cnt == 0 && x == 0) { start = c + 1; continue; }
-        const int add = 2 * WORDS_PER_CHUNK + 3 * x;
-        if (units + add > 2 * RANK_BUDGET && cnt > 0) {
-            f(start, c, cnt);
-            start = c;
-            units = 0;
-            cnt = 0;
+    for (int t = 0; t < nchunks; t += WAVE) {
+        const int xv = t + ln < nchunks ? (int)cc[t + ln] : 0;
+        const int n = min(WAVE, nchunks - t);
+        for (int j = 0; j < n; ++j) {
+            const int x = __builtin_amdgcn_readlane(xv, j);
+            const int c = t + j;
+            if (cnt == 0 && x == 0) { start = c + 1; continue; }
+            const int add = 2 * WORDS_PER_CHUNK + 3 * x;
+            if (units + add > 2 * RANK_BUDGET && cnt > 0) {
+                f(start, c, cnt);
+                start = c;
+                units = 0;
+                cnt = 0;
+            }
+            units += add;
+            cnt += x;
         }
-        units += add;
-        cnt += x;
     }
     if (cnt > 0) f(start, nchunks, cnt);
 }
 
-__global__ __launch_bounds__(256) void k_win_count(const HeavyRow *__restrict__ heavy, int nchunks,
-                                                   const uint32_t *__restrict__ chunk_cnt,
-                                                   uint32_t *__restrict__ whist, WsHdr *wh) {
-    const unsigned h = blockIdx.x * 256 + threadIdx.x;
-    if (h >= wh->n_heavy) return;
-    const HeavyRow hr = heavy[h];
-    const uint32_t *cc = chunk_cnt + (size_t)hr.slot * nchunks;
-    unsigned n = 0;
-    for (int c = 0; c < nchunks; ++c)
-        if (cc[c] > (uint32_t)CHUNK_COLS) atomicOr(&wh->err, ERR_CHUNK);
-    for_each_window(cc, nchunks, [&](int lo, int, int) {
-        atomicAdd(&whist[lo], 1u);
-        ++n;
-    });
-    atomicAdd(&wh->n_items, n);
+// Blocks of 16 heavy rows (one per wave); window counts per first chunk are
+// gathered in LDS first (one global atomic per chunk and block) when the
+// chunks fit LDS_WIN_CHUNKS.
+constexpr int LDS_WIN_CHUNKS = 4096;
+
+__global__ __launch_bounds__(1024) void k_win_count(const HeavyRow *__restrict__ heavy, int nchunks,
+                                                    const uint32_t *__restrict__ chunk_cnt,
+                                                    uint32_t *__restrict__ whist, WsHdr *wh) {
+    __shared__ uint32_t hist[LDS_WIN_CHUNKS];
+    __shared__ unsigned s_items;
+    const bool lds = nchunks <= LDS_WIN_CHUNKS;
+    const int tid = threadIdx.x, ln = tid & 63;
+    if (lds)
+        for (int c = tid; c < nchunks; c += 1024) hist[c] = 0u;
+    if (tid == 0) s_items = 0;
+    __syncthreads();
+    const unsigned h = blockIdx.x * 16 + (tid >> 6);
+    if (h < wh->n_heavy) {
+        const uint32_t *cc = chunk_cnt + (size_t)heavy[h].slot * nchunks;
+        bool wide = false;
+        for (int c = ln; c < nchunks; c += WAVE) wide |= cc[c] > (uint32_t)CHUNK_COLS;
+        if (wide) atomicOr(&wh->err, ERR_CHUNK);
+        unsigned n = 0;
+        wave_windows(cc, nchunks, [&](int lo, int, int) {
+            if (ln == 0) {
+                if (lds) atomicAdd(&hist[lo], 1u);
+                else atomicAdd(&whist[lo], 1u);
+            }
+            ++n;
+        });
+        if (ln == 0) atomicAdd(&s_items, n);
+    }
+    __syncthreads();
+    if (lds)
+        for (int c = tid; c < nchunks; c += 1024)
+            if (hist[c]) atomicAdd(&whist[c], hist[c]);
+    if (tid == 0 && s_items) atomicAdd(&wh->n_items, s_items);
 }
 
 // exclusive scan of the per-chunk window counts (one block)
@@ -421,21 +479,51 @@ __global__ __launch_bounds__(1024) void k_win_scan(uint32_t *__restrict__ whist,
     if (threadIdx.x == 0 && (unsigned)carry > cap) atomicOr(&wh->err, ERR_ITEMS);
 }
 
-__global__ __launch_bounds__(256) void k_win_emit(const HeavyRow *__restrict__ heavy, int nchunks,
-                                                  const uint32_t *__restrict__ chunk_cnt,
-                                                  const int64_t *__restrict__ rpts_C,
-                                                  const int32_t *__restrict__ rA,
-                                                  const uint32_t *__restrict__ wpos, uint32_t *__restrict__ wcur,
-                                                  WinItem *__restrict__ items, unsigned cap, WsHdr *wh) {
-    const unsigned h = blockIdx.x * 256 + threadIdx.x;
-    if (h >= wh->n_heavy || (wh->err & ERR_ITEMS)) return;
-    const HeavyRow hr = heavy[h];
-    const uint32_t *cc = chunk_cnt + (size_t)hr.slot * nchunks;
+// Windows laid out sorted by first chunk: a window's slot is its chunk's
+// start (wpos) plus a block base reserved with one atomic per chunk and block
+// plus its rank within the block (LDS), or one global atomic per window when
+// the chunks do not fit LDS.
+__global__ __launch_bounds__(1024) void k_win_emit(const HeavyRow *__restrict__ heavy, int nchunks,
+                                                   const uint32_t *__restrict__ chunk_cnt,
+                                                   const int64_t *__restrict__ rpts_C,
+                                                   const int32_t *__restrict__ rA,
+                                                   const uint32_t *__restrict__ wpos, uint32_t *__restrict__ wcur,
+                                                   WinItem *__restrict__ items, unsigned cap, WsHdr *wh) {
+    __shared__ uint32_t cntl[LDS_WIN_CHUNKS], basel[LDS_WIN_CHUNKS];
+    if (wh->err & ERR_ITEMS) return;                 // uniform over the grid
+    const bool lds = nchunks <= LDS_WIN_CHUNKS;
+    const int tid = threadIdx.x, ln = tid & 63;
+    const unsigned h = blockIdx.x * 16 + (tid >> 6);
+    const bool mine = h < wh->n_heavy;
+    HeavyRow hr{0, 0};
+    const uint32_t *cc = chunk_cnt;
+    if (mine) {
+        hr = heavy[h];
+        cc = chunk_cnt + (size_t)hr.slot * nchunks;
+    }
+    if (lds) {
+        for (int c = tid; c < nchunks; c += 1024) cntl[c] = 0u;
+        __syncthreads();
+        if (mine)
+            wave_windows(cc, nchunks, [&](int lo, int, int) {
+                if (ln == 0) atomicAdd(&cntl[lo], 1u);
+            });
+        __syncthreads();
+        for (int c = tid; c < nchunks; c += 1024) {
+            const uint32_t k = cntl[c];
+            if (k) basel[c] = atomicAdd(&wcur[c], k);
+            cntl[c] = 0u;
+        }
+        __syncthreads();
+    }
+    if (!mine) return;
     int64_t pos = rpts_C[hr.row];
     const int a0 = rA[hr.row], a1 = rA[hr.row + 1];
-    for_each_window(cc, nchunks, [&](int lo, int hi, int cnt) {
-        const unsigned at = wpos[lo] + atomicAdd(&wcur[lo], 1u);
-        if (at < cap) items[at] = WinItem{hr.row, lo, hi, cnt, pos, a0, a1, hr.slot, 0};
+    wave_windows(cc, nchunks, [&](int lo, int hi, int cnt) {
+        if (ln == 0) {
+            const unsigned at = wpos[lo] + (lds ? basel[lo] + atomicAdd(&cntl[lo], 1u) : atomicAdd(&wcur[lo], 1u));
+            if (at < cap) items[at] = WinItem{hr.row, lo, hi, cnt, pos, a0, a1, hr.slot, 0};
+        }
         pos += cnt;
     });
 }
@@ -911,10 +999,12 @@ hipError_t launch_validate(const CsrDev &a, int *err, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, PlanHdr *hdr, const BinLimits &L,
-                           hipStream_t s) {
+hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, uint32_t *edeg, PlanHdr *hdr,
+                           const BinLimits &L, hipStream_t s) {
     if (A.nrows == 0) return hipSuccess;
-    k_row_flop<<<grid1(A.nrows, 256), 256, 0, s>>>((int)A.nrows, A.rpts, A.cols, B.rpts, B.ncols, flop, hdr, L);
+    if (A.nnz > 0)
+        k_entry_deg<<<(unsigned)std::min<int64_t>(grid1(A.nnz, 256), 8192), 256, 0, s>>>(A.nnz, A.cols, B.rpts, edeg);
+    k_row_flop<<<grid1(A.nrows, 256), 256, 0, s>>>((int)A.nrows, A.rpts, edeg, B.ncols, flop, hdr, L);
     return hipGetLastError();
 }
 
@@ -995,10 +1085,10 @@ hipError_t launch_windows(unsigned nheavy_max, const HeavyRow *heavy, int nchunk
     if (nheavy_max == 0) return hipSuccess;
     hipError_t e = hipMemsetAsync(whist, 0, sizeof(uint32_t) * 2 * (size_t)nchunks, s);   // whist and wcur
     if (e != hipSuccess) return e;
-    k_win_count<<<grid1(nheavy_max, 256), 256, 0, s>>>(heavy, nchunks, chunk_cnt, whist, wh);
+    k_win_count<<<grid1(nheavy_max, 16), 1024, 0, s>>>(heavy, nchunks, chunk_cnt, whist, wh);
     k_win_scan<<<1, 1024, 0, s>>>(whist, nchunks, cap, wh);
-    k_win_emit<<<grid1(nheavy_max, 256), 256, 0, s>>>(heavy, nchunks, chunk_cnt, rpts_C, rA, whist, wcur, items, cap,
-                                                       wh);
+    k_win_emit<<<grid1(nheavy_max, 16), 1024, 0, s>>>(heavy, nchunks, chunk_cnt, rpts_C, rA, whist, wcur, items, cap,
+                                                      wh);
     return hipGetLastError();
 }
 

@@ -157,6 +157,30 @@ def test_wide_columns_multipass_bitmap(sp):
             assert_matches(C, oracle.spgemm(A, B, sorted_output=srt), srt)
 
 
+def test_very_wide_columns_global_window_counters(sp):
+    """More than 4096 column chunks (17,000,000 columns): the window split
+    counts windows per first chunk in global memory instead of LDS."""
+    _note("case very_wide_columns")
+    import torch
+    k = 17_000_000
+    B = erdos_renyi_fixed_degree(4000, 24, 11, ncols=k)
+    rng = np.random.default_rng(12)
+    rows = [np.sort(rng.choice(4000, size=s, replace=False)) for s in (2500, 900, 5, 0, 1200)]
+    rp = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum([r.size for r in rows], out=rp[1:])
+    A = with_values(CSR(len(rows), 4000, rp, np.concatenate(rows).astype(np.int32), None), 13, "f64")
+    dA, dB = _dev(sp, A), _dev(sp, B)
+    for srt in (True, False):
+        p = sp.Plan([dA], [dB], sorted_output=srt)
+        p.symbolic()
+        C = p.numeric()[0]
+        torch.cuda.synchronize()
+        st = p.stats(0)
+        assert st["status"] == 0 and st["heavy_rows"] >= 3
+        p.close()
+        assert_matches(C, oracle.spgemm(A, B, sorted_output=srt, nthreads=2), srt)
+
+
 def test_rectangular_tall_skinny_bfs(sp):
     """Multi-source BFS step: R-MAT scale 14 (int64 ones) times a frontier stack."""
     _note("case bfs")
