@@ -39,6 +39,8 @@ WORKLOADS = {
                        "unsorted output", sorted=False),
     "serve": dict(desc="served stream: Poisson arrivals, n log-uniform [256, 131072], nnz/row U{2..32}, "
                        "ER/R-MAT 50/50, sorted/unsorted 50/50, A and B independent, FP64", sorted=None),
+    "batch": dict(desc="small stratum of the served stream (n*d^2 <= 2^20): the products of one batch through "
+                       "the batched path vs one launch sequence per product", sorted=None),
 }
 
 
@@ -98,9 +100,9 @@ def main():
         sys.exit(2)
 
     host_serve = None
-    if args.workload == "serve":
+    if args.workload in ("serve", "batch"):
         # operands are generated on a host process pool before anything touches the GPU
-        host_serve = _generate_serve(args)
+        host_serve = _generate_serve(args, small_only=args.workload == "batch")
 
     import torch
     import paper_1804_01698_amd as sp
@@ -112,6 +114,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "serve":
         return bench_serve(args, sp, dev, *host_serve)
+    if args.workload == "batch":
+        return bench_batch(args, sp, dev, host_serve[1])
 
     t_gen = time.perf_counter()
     inp = make_inputs(args.workload, args.seed, args.sorted_flag)
@@ -321,13 +325,13 @@ def _gen_request(r):
     return r, a, b
 
 
-def _generate_serve(args):
+def _generate_serve(args, small_only: bool = False):
     """Requests of the served stream and of its small stratum, with their
     operands generated on a host process pool (16 workers at most)."""
     import multiprocessing as mp
     from synth import serving_stream
     t = time.perf_counter()
-    reqs = serving_stream(args.requests, args.seed)
+    reqs = [] if small_only else serving_stream(args.requests, args.seed)
     small = serving_stream(args.small_requests, args.seed + 1000, max_flop=2 ** 20)
     workers = max(1, min(16, os.cpu_count() or 1))
     with mp.get_context("spawn").Pool(workers) as pool:
@@ -342,6 +346,62 @@ def _upload(sp, ops, dev):
     from paper_1804_01698_amd.serve import Request
     return [Request(r.rid, r.arrival_s, sp.DeviceCSR.from_host(a, device=dev), sp.DeviceCSR.from_host(b, device=dev),
                     r.sorted_out) for r, a, b in ops]
+
+
+def bench_batch(args, sp, dev, small_ops):
+    """The small stratum as one batch: analyse once, then K timed runs of the
+    batch (kernels only, products outside the batched range go through the
+    plan path on a second stream), against one launch sequence per product."""
+    import torch
+    from paper_1804_01698_amd.serve import serial_products
+    reqs = _upload(sp, small_ops, dev)
+    As, Bs, fl = [r.A for r in reqs], [r.B for r in reqs], [r.sorted_out for r in reqs]
+    bt = sp.Batch(As, Bs, fl)                      # first construction warms the allocator
+    del bt
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bt = sp.Batch(As, Bs, fl)
+    torch.cuda.synchronize()
+    t_analyse = time.perf_counter() - t
+    rest = [r for r, ok in zip(reqs, bt.supported) if not ok]
+    side = torch.cuda.Stream()
+
+    def step():
+        # the batch runs on the current stream while the products outside its
+        # range go through the plan path on a second stream
+        bt.run()
+        with torch.cuda.stream(side):
+            for r in rest:
+                p = sp.Plan([r.A], [r.B], sorted_output=r.sorted_out, stream=side)
+                p.symbolic()
+                p.numeric()
+                side.synchronize()
+                p.close()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    serial_products(reqs[:8])
+    ts = min(serial_products(reqs) for _ in range(2))
+    flop = sum(bt.flop)
+    out = {
+        "metric": METRIC, "value": round(len(reqs) / dt, 1), "unit": "products/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch: {WORKLOADS['batch']['desc']}", "products": len(reqs),
+                   "outside_batched_range": len(rest), "flop": flop, "seed": args.seed},
+        "batched_gflops": round(2.0 * flop / dt / 1e9, 2),
+        "analyse_ms": round(t_analyse * 1e3, 3),
+        "serial_ms": round(ts * 1e3, 3),
+        "speedup_vs_serial": round(ts / dt, 2),
+        "speedup_incl_analyse": round(ts / (dt + t_analyse), 2),
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_serve(args, sp, dev, main_ops, small_ops):

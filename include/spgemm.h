@@ -237,11 +237,12 @@ int spgemm_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t st
  * product path uses for that bound (Section 4.2.1); its entries are staged in
  * a bound-sized slot of a caller-provided arena and then compacted into CSR
  * inside the arena: the one-phase scheme of Section 2 (allocate an upper
- * bound, then compact).  Rows whose key bound exceeds 8448 are outside the
- * batched range: their product gets status SPGEMM_ERR_UNSUPPORTED (use the
- * plan path for it).  Operands must be valid CSR (see spgemm_csr); the batch
- * path does not validate them.  The total row count of a batch must be below
- * 2^31 - 1.  Calls that overlap on one scratch or arena race.
+ * bound, then compact).  A product with a row whose key bound exceeds 8448 is
+ * outside the batched range: none of its rows is computed and it gets status
+ * SPGEMM_ERR_UNSUPPORTED (use the plan path for it).  Operands must be valid
+ * CSR (see spgemm_csr); the batch path does not validate them.  The total row
+ * count of a batch must be below 2^31 - 1.  Calls that overlap on one scratch
+ * or arena race.
  */
 typedef struct {
     int64_t flop;       /* multiplications of the product                           */

@@ -121,8 +121,9 @@ __global__ void k_bat_binscan(BatchCounters c) {
     }
 }
 
-// Rows go to their bin's list as {row, product, A range}; empty rows and rows
-// out of range get count 0 (and the latter mark their product unsupported).
+// Rows go to their bin's list as {row, product, A range}; empty rows and all
+// rows of a product with a row out of range get count 0 (the latter mark
+// their product unsupported).  bcur ends as the number of rows listed per bin.
 __global__ __launch_bounds__(256) void k_bat_scatter(int64_t mtot, BatchRows r, BatchCounters c,
                                                      int4 *__restrict__ list, uint32_t *__restrict__ nnz) {
     __shared__ unsigned hist[BAT_NB], base[BAT_NB];
@@ -133,11 +134,16 @@ __global__ __launch_bounds__(256) void k_bat_scatter(int64_t mtot, BatchRows r, 
     unsigned rank = 0;
     if (g < mtot) {
         b = r.bin[g];
-        if (b >= 1 && b <= BAT_TOP) {
+        const int p = r.pid[g];
+        // a product with any row out of range is left to the caller whole
+        const bool skip = c.pmax[p] > (unsigned long long)BATCH_XMAX;
+        if (b >= 1 && b <= BAT_TOP && !skip) {
             rank = atomicAdd(&hist[b], 1u);
         } else {
             nnz[g] = 0;
-            if (b > BAT_TOP) c.pstatus[r.pid[g]] = SPGEMM_ERR_UNSUPPORTED;
+            r.kx[g] = 0u;
+            if (skip) c.pstatus[p] = SPGEMM_ERR_UNSUPPORTED;
+            b = -1;
         }
     }
     __syncthreads();
@@ -211,7 +217,7 @@ __global__ __launch_bounds__(G) void k_bat_hash(const BatchDesc *__restrict__ d,
     __shared__ V vals[T];
     __shared__ SegLds<G, true, V> sg;
     const int tid = threadIdx.x;
-    const unsigned n = c.bcnt[bin];
+    const unsigned n = c.bcur[bin];             // rows actually listed
     const int4 *lst = list + c.boff[bin];
     int ovf = 0;
     for (unsigned it = blockIdx.x; it < n; it += gridDim.x) {
