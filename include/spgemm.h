@@ -221,6 +221,22 @@ int spgemm_masked_sum_i64(int64_t nrows, int64_t ncols, const int64_t *rpts_C, c
                           const int64_t *vals_C, const spgemm_csr *M, int64_t *out, hipStream_t stream);
 
 /*
+ * Masked product sum without forming C (the masked product behind Section
+ * 5.6's triangle count): out[0] = sum over the stored positions (i, j) of M of
+ * (A*B)_ij, int64 wrap-around; every product a_ik*b_kj whose column j is not in
+ * row i of M is dropped as it is formed.  A is m x n, B is n x k, M is m x k
+ * (a pattern: its vals are ignored; a row must not repeat a column).  int64
+ * values; if A.vals or B.vals is NULL every value of both counts as 1
+ * (counting: triangles = spgemm_masked_product_sum_i64(L, U, A) / 2).
+ * workspace: device buffer of at least SPGEMM_MASKED_WS_BYTES bytes (a row
+ * counter), out: device int64 (overwritten).  Asynchronous on stream; no
+ * device allocation.  Errors: SPGEMM_ERR_INVALID_ARG, SPGEMM_ERR_SHAPE.
+ */
+enum { SPGEMM_MASKED_WS_BYTES = 256 };
+int spgemm_masked_product_sum_i64(const spgemm_csr *A, const spgemm_csr *B, const spgemm_csr *M, void *workspace,
+                                  int64_t *out, hipStream_t stream);
+
+/*
  * Streaming copy of nbytes (multiple of 16) from src to dst, both device
  * pointers: the measured HBM copy rate is the denominator the benchmark
  * compares the SpGEMM byte rates with.  Asynchronous on stream.

@@ -79,6 +79,9 @@ def _load():
     lib.spgemm_plan_kernel_times.argtypes = [P, ctypes.POINTER(_KTime), ctypes.c_int]
     lib.spgemm_masked_sum_i64.restype = ctypes.c_int
     lib.spgemm_masked_sum_i64.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, ctypes.POINTER(_Csr), P, P]
+    lib.spgemm_masked_product_sum_i64.restype = ctypes.c_int
+    lib.spgemm_masked_product_sum_i64.argtypes = [ctypes.POINTER(_Csr), ctypes.POINTER(_Csr), ctypes.POINTER(_Csr),
+                                                  P, P, P]
     lib.spgemm_stream_copy.restype = ctypes.c_int
     lib.spgemm_stream_copy.argtypes = [P, P, ctypes.c_size_t, P]
     lib.spgemm_batch_scratch_bytes.restype = ctypes.c_size_t
@@ -420,8 +423,37 @@ def masked_sum_i64(C: DeviceCSR, M: DeviceCSR, stream=None) -> int:
     return int(out.item())
 
 
-def triangle_count(A: DeviceCSR, L: DeviceCSR, U: DeviceCSR, stream=None) -> int:
-    """Triangles of the undirected graph A: sum(C o A) / 2 with C = L*U (int64, sorted rows)."""
+MASKED_WS_BYTES = 256
+
+
+def masked_product_sum_i64(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, ones: bool = False, stream=None) -> int:
+    """Sum of (A*B)_ij over the positions stored in M, without forming A*B
+    (int64, wrap-around).  ones=True counts products (every value 1)."""
+    dev = A.rpts.device
+    ws = torch.empty(MASKED_WS_BYTES, dtype=torch.uint8, device=dev)
+    out = torch.empty(1, dtype=torch.int64, device=dev)
+    ca, cb = A._c(), B._c()
+    if ones:
+        ca.vals = None
+        cb.vals = None
+    m = _Csr(M.nrows, M.ncols, M.nnz, M.rpts.data_ptr(), M.cols.data_ptr() if M.nnz else None, None)
+    st = _lib.spgemm_masked_product_sum_i64(ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(m),
+                                            ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                            _stream_handle(stream))
+    _check(st, "spgemm_masked_product_sum_i64")
+    return int(out.item())
+
+
+def triangle_count(A: DeviceCSR, L: DeviceCSR, U: DeviceCSR, stream=None, fused: bool = True) -> int:
+    """Triangles of the undirected graph A: sum(C o A) / 2 with C = L*U.  fused
+    (default): the masked product counts L*U's products that land on A's pattern
+    without forming C; otherwise C is formed (int64, sorted rows) and summed
+    over A's pattern."""
+    if fused:
+        s = masked_product_sum_i64(L, U, A, ones=True, stream=stream)
+        if s % 2:
+            raise SpgemmError(-10, "masked count of L*U over symmetric A is odd")
+        return s // 2
     C = spgemm(L, U, sorted_output=True, stream=stream)
     s = masked_sum_i64(C, A, stream)
     if s % 2:

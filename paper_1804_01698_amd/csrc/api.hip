@@ -556,6 +556,24 @@ int spgemm_masked_sum_i64(int64_t nrows, int64_t ncols, const int64_t *rpts_C, c
     return SPGEMM_OK;
 }
 
+int spgemm_masked_product_sum_i64(const spgemm_csr *A, const spgemm_csr *B, const spgemm_csr *M, void *workspace,
+                                  int64_t *out, hipStream_t stream) {
+    if (!A || !B || !M || !workspace || !out) return SPGEMM_ERR_INVALID_ARG;
+    if (!csr_ok(*A) || !csr_ok(*B) || !csr_ok(*M)) return SPGEMM_ERR_INVALID_ARG;
+    if (A->ncols != B->nrows || M->nrows != A->nrows || M->ncols != B->ncols) return SPGEMM_ERR_SHAPE;
+    const bool ones = !A->vals || !B->vals;
+    int ncu = 256;
+    {
+        int devid = 0, n = 0;
+        if (hipGetDevice(&devid) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, devid) == hipSuccess && n > 0)
+            ncu = n;
+    }
+    HIPCK(launch_masked_product(dev(*A), dev(*B), dev(*M), ones, (unsigned *)workspace, out, ncu, stream),
+          "masked_product");
+    return SPGEMM_OK;
+}
+
 int spgemm_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t stream) {
     if ((nbytes % 16) != 0 || (nbytes > 0 && (!dst || !src))) return SPGEMM_ERR_INVALID_ARG;
     HIPCK(launch_stream_copy(dst, src, nbytes, stream), "stream_copy");

@@ -915,6 +915,84 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
     if (bad) atomicOr(&wh->err, ERR_COUNT);
 }
 
+// ----------------------------------------------------------------------- masked product sum
+
+// Sum of C_ij over the positions (i, j) of a mask M with C = A*B, without
+// forming C (the masked product of Section 5.6's triangle count: keep a_ik*b_kj
+// only where (i, j) is in M).  A persistent grid claims rows of A; a block sets
+// the row's mask columns in an LDS bitmap over a pass of NWORDS*32 columns,
+// keeps the products whose column bit is set (int64, wrap-around; all values 1
+// when ONES) and clears the bits again.  One atomic per block at the end.
+constexpr int U_MASK = 8;
+
+template <int NWORDS, bool ONES>
+__global__ __launch_bounds__(1024) void k_masked_product(int m, int64_t ncols, const int32_t *__restrict__ rA,
+                                                         const int32_t *__restrict__ cA,
+                                                         const unsigned long long *__restrict__ vA,
+                                                         const int32_t *__restrict__ rB,
+                                                         const int32_t *__restrict__ cB,
+                                                         const unsigned long long *__restrict__ vB,
+                                                         const int32_t *__restrict__ rM,
+                                                         const int32_t *__restrict__ cM, unsigned *next_row,
+                                                         unsigned long long *out) {
+    constexpr int G = 1024;
+    constexpr int64_t WIN = (int64_t)NWORDS * 32;
+    using V = unsigned long long;
+    __shared__ uint32_t bm[NWORDS];
+    __shared__ SegLds<G, !ONES, V> sg;
+    __shared__ int s_row;
+    __shared__ V s_part[G / WAVE];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < NWORDS; i += G) bm[i] = 0u;
+    V acc = 0;
+    const int npass = (int)((ncols + WIN - 1) / WIN);
+    for (;;) {
+        if (tid == 0) s_row = (int)atomicAdd(next_row, 1u);
+        __syncthreads();                               // also orders the bitmap clear
+        const int row = s_row;
+        __syncthreads();                               // everyone has read s_row
+        if (row >= m) break;                           // uniform over the block
+        const int a0 = rA[row], a1 = rA[row + 1], m0 = rM[row], m1 = rM[row + 1];
+        if (a0 == a1 || m0 == m1) continue;            // uniform: nothing to add
+        for (int pass = 0; pass < npass; ++pass) {
+            const int64_t c0 = (int64_t)pass * WIN;
+            for (int p = m0 + tid; p < m1; p += G) {
+                const uint32_t off = (uint32_t)((int64_t)cM[p] - c0);
+                if (off < (uint32_t)WIN) atomicOr(&bm[off >> 5], 1u << (off & 31));
+            }
+            __syncthreads();
+            enum_row<G, U_MASK, !ONES, V>(
+                a0, a1, cA, vA, sg, [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
+                [&](const int (&q)[U_MASK], const bool (&ok)[U_MASK], const V (&av)[U_MASK]) {
+#pragma unroll
+                    for (int u = 0; u < U_MASK; ++u) {
+                        const int c = cB[q[u]];                   // q is always a valid index
+                        V b = 1;
+                        if constexpr (!ONES) b = vB[q[u]];
+                        const uint32_t off = (uint32_t)((int64_t)c - c0);
+                        const bool hit = ok[u] && off < (uint32_t)WIN && ((bm[off >> 5] >> (off & 31)) & 1u);
+                        if constexpr (ONES) acc += hit ? 1ull : 0ull;
+                        else acc += hit ? av[u] * b : 0ull;
+                    }
+                });
+            __syncthreads();
+            for (int p = m0 + tid; p < m1; p += G) {
+                const uint32_t off = (uint32_t)((int64_t)cM[p] - c0);
+                if (off < (uint32_t)WIN) bm[off >> 5] = 0u;
+            }
+            __syncthreads();
+        }
+    }
+    acc = wave_sum_u64(acc);
+    if ((tid & 63) == 0) s_part[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        V t = 0;
+        for (int w = 0; w < G / WAVE; ++w) t += s_part[w];
+        if (t) atomicAdd(out, t);
+    }
+}
+
 // ----------------------------------------------------------------------- masked sum
 
 __device__ __forceinline__ bool lds_contains(const int *tab, uint32_t T, int key) {
@@ -1189,6 +1267,37 @@ hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, c
             items, nitems, A.cols, (const unsigned long long *)A.vals, B.rpts, long_id, idx, nchunks, bc,
             (const unsigned long long *)bv, cC, (unsigned long long *)vC, bmap, wh);
     }
+    return hipGetLastError();
+}
+
+template <int NWORDS, bool ONES>
+static void masked_product_l(const CsrDev &A, const CsrDev &B, const CsrDev &M, unsigned *next_row,
+                             unsigned long long *out, int ncu, hipStream_t s) {
+    static const int occ = blocks_per_cu(k_masked_product<NWORDS, ONES>, 1024);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(A.nrows, (int64_t)ncu * occ));
+    k_masked_product<NWORDS, ONES><<<grid, 1024, 0, s>>>(
+        (int)A.nrows, B.ncols, A.rpts, A.cols, (const unsigned long long *)A.vals, B.rpts, B.cols,
+        (const unsigned long long *)B.vals, M.rpts, M.cols, next_row, out);
+}
+
+template <bool ONES>
+static void masked_product_t(const CsrDev &A, const CsrDev &B, const CsrDev &M, unsigned *next_row,
+                             unsigned long long *out, int ncu, hipStream_t s) {
+    // bitmap tiers: 64 K, 256 K, 1 M columns per pass (the largest leaves room
+    // for the multipliers in LDS)
+    const int64_t need = (B.ncols + 31) / 32;
+    if (need <= BM_WORDS_SMALL) masked_product_l<BM_WORDS_SMALL, ONES>(A, B, M, next_row, out, ncu, s);
+    else if (need <= BM_WORDS_MID) masked_product_l<BM_WORDS_MID, ONES>(A, B, M, next_row, out, ncu, s);
+    else masked_product_l<32768, ONES>(A, B, M, next_row, out, ncu, s);
+}
+
+hipError_t launch_masked_product(const CsrDev &A, const CsrDev &B, const CsrDev &M, bool ones, unsigned *next_row,
+                                 int64_t *out, int ncu, hipStream_t s) {
+    k_zero_u64<<<1, 1, 0, s>>>((unsigned long long *)out);
+    k_zero_u32n<<<1, 64, 0, s>>>(next_row, 1);
+    if (A.nrows == 0) return hipGetLastError();
+    if (ones) masked_product_t<true>(A, B, M, next_row, (unsigned long long *)out, ncu, s);
+    else masked_product_t<false>(A, B, M, next_row, (unsigned long long *)out, ncu, s);
     return hipGetLastError();
 }
 

@@ -51,6 +51,8 @@ hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, c
                              const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
                              const void *bv, int32_t *cC, void *vC, const uint32_t *bmap, WsHdr *wh, int ncu,
                              hipStream_t s);
+hipError_t launch_masked_product(const CsrDev &A, const CsrDev &B, const CsrDev &M, bool ones, unsigned *next_row,
+                                 int64_t *out, int ncu, hipStream_t s);
 hipError_t launch_masked_sum(int64_t m, int64_t ncols, const int64_t *rC, const int32_t *cC, const int64_t *vC,
                              const CsrDev &M, int64_t *out, hipStream_t s);
 hipError_t launch_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t s);

@@ -200,6 +200,7 @@ def test_triangles(sp, degree_order):
     A, L, U = triangle_inputs(g, degree_order=degree_order)
     t = sp.triangle_count(_dev(sp, A), _dev(sp, L), _dev(sp, U))
     assert t == oracle.triangle_count(A, L, U)
+    assert sp.triangle_count(_dev(sp, A), _dev(sp, L), _dev(sp, U), fused=False) == t
     C = _run(sp, L, U, True)
     assert_matches(C, oracle.spgemm(L, U, sorted_output=True), True)
 
@@ -215,6 +216,50 @@ def test_triangles_closed_form(sp):
     d[4:, :4] = 1
     A, L, U = triangle_inputs(from_dense(d))
     assert sp.triangle_count(_dev(sp, A), _dev(sp, L), _dev(sp, U)) == 0
+
+
+def _mask(m, k, dens, seed):
+    """A random pattern (no repeated column in a row), values irrelevant."""
+    return random_sparse(m, k, dens, seed, values="ones")
+
+
+@pytest.mark.parametrize("m,n,k,da,db,dm,seed", [
+    (1, 1, 1, 1.0, 1.0, 1.0, 0), (40, 30, 50, 0.2, 0.2, 0.3, 1), (300, 200, 400, 0.05, 0.05, 0.1, 2),
+    (120, 90, 70, 0.4, 0.3, 0.05, 3), (64, 64, 64, 0.0, 0.5, 0.5, 4), (50, 60, 70, 0.3, 0.3, 0.0, 5)])
+def test_masked_product_values(sp, m, n, k, da, db, dm, seed):
+    """Masked product sum with int64 values (wrap-around) against the explicit
+    product summed over the mask."""
+    _note(f"case masked_product m={m} n={n} k={k} seed={seed}")
+    A = with_values(random_sparse(m, n, da, seed, values=""), seed + 1, "i64", lo=-(2**40), hi=2**40)
+    B = with_values(random_sparse(n, k, db, seed + 2, values=""), seed + 3, "i64", lo=-(2**40), hi=2**40)
+    M = _mask(m, k, dm, seed + 4)
+    want = oracle.masked_sum(oracle.spgemm(A, B, sorted_output=True), M)
+    got = sp.masked_product_sum_i64(_dev(sp, A), _dev(sp, B), _dev(sp, M))
+    assert got == want
+    ones = lambda X: with_values(X, 0, "ones")
+    want1 = oracle.masked_sum(oracle.spgemm(ones(A), ones(B), sorted_output=True), M)
+    assert sp.masked_product_sum_i64(_dev(sp, A), _dev(sp, B), _dev(sp, M), ones=True) == want1
+
+
+def test_masked_product_wide_multipass(sp):
+    """2,500,000 columns: the mask bitmap sweeps three passes."""
+    _note("case masked_product wide")
+    k = 2_500_000
+    B = with_values(erdos_renyi_fixed_degree(2000, 16, 21, ncols=k, values=""), 22, "i64", lo=1, hi=9)
+    A = with_values(random_sparse(300, 2000, 0.01, 23, values=""), 24, "i64", lo=1, hi=9)
+    # the mask holds half of each row's product columns plus unrelated columns
+    C = oracle.spgemm(A, B, sorted_output=True)
+    rng = np.random.default_rng(25)
+    rows = []
+    for i in range(C.nrows):
+        cols = C.cols[C.rpts[i]:C.rpts[i + 1]]
+        keep = cols[rng.random(cols.size) < 0.5]
+        extra = rng.choice(k, 5, replace=False)
+        rows.append(np.unique(np.concatenate([keep, extra])).astype(np.int32))
+    rp = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum([r.size for r in rows], out=rp[1:])
+    M = CSR(len(rows), k, rp, np.concatenate(rows), np.ones(int(rp[-1]), dtype=np.int64))
+    assert sp.masked_product_sum_i64(_dev(sp, A), _dev(sp, B), _dev(sp, M)) == oracle.masked_sum(C, M)
 
 
 def test_repeat_runs_identical_pattern(sp):

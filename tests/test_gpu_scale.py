@@ -91,9 +91,10 @@ def test_rmat_scale18_sorted(sp):
 
 
 def test_triangles_scale18(sp):
-    """Triangle count on symmetric R-MAT scale 18 ef 16: natural-order L*U on the
-    GPU (2.4e9 entries) against the oracle on the degree-ordered graph (the
-    count does not depend on the vertex order), and the degree order on both."""
+    """Triangle count on symmetric R-MAT scale 18 ef 16: the fused masked count
+    in natural order (L*U would hold 2.4e9 entries) and degree order, and the
+    formed product in degree order, against the oracle on the degree-ordered
+    graph (the count does not depend on the vertex order)."""
     _note("case triangles scale 18")
     g = symmetric_rmat_graph(18, 16, 1)
     A0, L0, U0 = triangle_inputs(g, degree_order=False)
@@ -104,6 +105,7 @@ def test_triangles_scale18(sp):
     assert t1 == ref
     t0 = sp.triangle_count(dev(A0), dev(L0), dev(U0))
     assert t0 == ref
+    assert sp.triangle_count(dev(A1), dev(L1), dev(U1), fused=False) == ref
     _note(f"triangles: {ref}")
 
 
