@@ -92,7 +92,7 @@ def main():
                     help="target oracle time of the CPU baseline's row sample")
     ap.add_argument("--requests", type=int, default=4000, help="serve: requests in the stream")
     ap.add_argument("--small-requests", type=int, default=256, help="serve: requests of the small stratum")
-    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: admission budget")
+    ap.add_argument("--budget-gb", type=float, default=128.0, help="serve: admission budget")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel HIP events")
     args = ap.parse_args()
 
@@ -467,6 +467,7 @@ def bench_serve(args, sp, dev, main_ops, small_ops):
 
     # warm-up: kernels loaded, allocator primed
     Server(budget).run(dreqs[:32], realtime=False)
+    torch.cuda.empty_cache()
     sat = Server(budget).run(dreqs, realtime=False)
     ssum = sat.summary()
     mu = ssum["products_per_s"]
@@ -477,9 +478,13 @@ def bench_serve(args, sp, dev, main_ops, small_ops):
         lam = frac * mu
         scale = base_rate / lam
         rq = [Request(r.rid, r.arrival_s * scale, r.A, r.B, r.sorted_out) for r in dreqs]
+        torch.cuda.empty_cache()                   # each run starts from a clean allocator
         rep = Server(budget).run(rq, realtime=True)
         loads[f"{frac}mu"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.summary().items()}
         loads[f"{frac}mu"]["lambda_per_s"] = round(lam, 1)
+        slow = sorted(rep.completions, key=lambda c: -c.latency_s)[:5]
+        loads[f"{frac}mu"]["slowest"] = [{"rid": c.rid, "path": c.path, "flop": c.flop,
+                                          "latency_ms": round(c.latency_s * 1e3, 1)} for c in slow]
         log(f"serve at {frac} mu: {loads[f'{frac}mu']}")
     del dreqs
 

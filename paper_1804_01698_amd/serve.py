@@ -17,9 +17,13 @@ share the GPU, each on a stream of its own:
 Admission: every device buffer a worker allocates for a request (scratch,
 arena, workspace, row pointers, output) is first reserved against one byte
 budget; a reservation that does not fit waits until others are released.
-A batch larger than the budget is split into consecutive groups in arrival
-order.  A request that cannot fit the budget even alone fails with a
-MemoryError status instead of waiting forever.
+The batch worker never waits while holding a reservation (its arena is only
+tried; on failure the batch is re-formed in groups reserved in one step);
+plan workers reserve workspace, then the exact output, under a stage lock, so
+at most one worker ever waits while holding memory.  A batch larger than the
+budget is split into consecutive groups in arrival order.  A request that
+cannot fit the budget even alone fails with a status instead of waiting
+forever.
 
 The GPU work itself is done by the library's kernels; this module only
 schedules calls to it.
@@ -118,6 +122,14 @@ class MemoryGate:
             self.used += n
             self.peak = max(self.peak, self.used)
 
+    def try_acquire(self, n: int) -> bool:
+        with self._cv:
+            if self.used + n > self.budget:
+                return False
+            self.used += n
+            self.peak = max(self.peak, self.used)
+            return True
+
     def release(self, n: int):
         with self._cv:
             self.used -= n
@@ -202,26 +214,25 @@ class Server:
         return reqs
 
     def _serve_batch(self, reqs: List[Request], stream):
+        # The batch worker never waits while it holds a reservation: scratch is
+        # reserved on its own, the arena only tried; if it does not fit, the
+        # analysis is dropped and the batch goes in groups reserved whole.
         As = [r.A for r in reqs]
         Bs = [r.B for r in reqs]
         flags = [r.sorted_out for r in reqs]
         sb = batch_scratch_bytes(As)
-        with self._admit:
-            self.gate.acquire(sb)
-            try:
-                an = Batch(As, Bs, flags, stream=stream, allocate=False)
-            except BaseException:
-                self.gate.release(sb)
-                raise
-            ok = [self._batchable(an, i, reqs[i]) for i in range(len(reqs))]
-            small = [i for i in range(len(reqs)) if ok[i]]
-            big = [i for i in range(len(reqs)) if not ok[i]]
-            whole = not big and self.gate.fits(sb + an.arena_bytes)
-            if whole:
-                self.gate.acquire(an.arena_bytes)
+        self.gate.acquire(sb)
+        try:
+            an = Batch(As, Bs, flags, stream=stream, allocate=False)
+        except BaseException:
+            self.gate.release(sb)
+            raise
+        ok = [self._batchable(an, i, reqs[i]) for i in range(len(reqs))]
+        small = [i for i in range(len(reqs)) if ok[i]]
+        big = [i for i in range(len(reqs)) if not ok[i]]
         for i in big:
             self._plan_q_put((reqs[i], an.flop[i]))
-        if whole:
+        if small and not big and self.gate.try_acquire(an.arena_bytes):
             try:
                 self._run_group(an, reqs, stream)
             finally:
@@ -244,8 +255,7 @@ class Server:
                 for r in sub:
                     self._done(r, "batch", 0, 0, -9, None)
                 continue
-            with self._admit:
-                self.gate.acquire(gs + ga)
+            self.gate.acquire(gs + ga)                 # one step: nothing held while waiting
             try:
                 bt = Batch([r.A for r in sub], [r.B for r in sub], [r.sorted_out for r in sub], stream=stream,
                            allocate=False)
@@ -296,11 +306,12 @@ class Server:
         ps = plan_scratch_bytes([req.A])
         held = 0
         try:
-            # A worker holds the admission lock from its first reservation to
-            # its last, so two workers never wait on each other's partial
-            # reservations; waits inside it are for memory that running work
-            # releases without needing the lock.
-            with self._admit:
+            # Plan workers take the stage lock from their first reservation to
+            # their last, so at most one worker waits while holding a partial
+            # reservation; the memory it waits for is held by fully admitted
+            # work (the batch worker never waits while holding any), which
+            # finishes without the lock.
+            with self._stage:
                 self.gate.acquire(ps)
                 held = ps
                 p = Plan([req.A], [req.B], sorted_output=req.sorted_out, stream=stream, defer_workspace=True)
@@ -332,7 +343,7 @@ class Server:
         self._cv = threading.Condition()
         self._pcv = threading.Condition()
         self._lock = threading.Lock()
-        self._admit = threading.Lock()     # held from a worker's first reservation to its last
+        self._stage = threading.Lock()     # a plan worker's reservation sequence
         self._closed = False
         self._completions: List[Completion] = []
         self._errors: List[str] = []

@@ -50,3 +50,13 @@ def test_memory_gate_rejects_oversize():
     with pytest.raises(MemoryError):
         g.acquire(11)
     assert g.fits(10) and not g.fits(11)
+
+
+def test_memory_gate_try_acquire_never_waits():
+    g = MemoryGate(100)
+    assert g.try_acquire(60)
+    assert not g.try_acquire(50)           # would exceed: refused at once
+    assert g.used == 60 and g.waits == 0
+    assert g.try_acquire(40) and g.used == 100 and g.peak == 100
+    g.release(100)
+    assert g.used == 0
