@@ -608,6 +608,15 @@ __global__ __launch_bounds__(256) void k_gather_vals(int64_t n, const int32_t *_
 
 // ----------------------------------------------------------------------- numeric
 
+// LDS of a numeric hash block besides its table: the enumeration state, and
+// (512-thread bins) extra words so that the idle enumeration LDS plus them can
+// hold a rank bitmap of 64 K columns for sorted output.
+template <int G, typename V>
+struct NumLds {
+    SegLds<G, true, V> sg;
+    uint2 extra[G == 512 ? 1024 : 1];
+};
+
 template <int G, int T, int U, bool SORTED, typename V>
 __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm, int64_t perm_off,
                                                 const int32_t *__restrict__ rA,
@@ -618,10 +627,12 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
                                                 const V *__restrict__ vB,
                                                 const int64_t *__restrict__ rpts_C,
                                                 int32_t *__restrict__ cC, V *__restrict__ vC,
-                                                WsHdr *wh, uint32_t hmul) {
+                                                WsHdr *wh, uint32_t hmul, int64_t ncolsB) {
     __shared__ __align__(16) int keys[T];
     __shared__ V vals[T];
-    __shared__ SegLds<G, true, V> sg;
+    __shared__ __align__(16) NumLds<G, V> lds;
+    __shared__ int rank_ws[G / WAVE + 1];
+    SegLds<G, true, V> &sg = lds.sg;
     const int tid = threadIdx.x;
     const int row = perm[perm_off + blockIdx.x];
     for (int i = tid; i < T; i += G) { keys[i] = -1; vals[i] = V(0); }
@@ -651,6 +662,50 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
     }
     const int64_t o = rpts_C[row];
     const int expected = (int)(rpts_C[row + 1] - o);
+    if constexpr (SORTED && G >= 512) {
+        // Sorted output of a wide bin by rank instead of a bitonic sort, when
+        // the columns of C fit a bitmap in the (now idle) enumeration LDS:
+        // occupied keys set their bit, an exclusive popcount prefix per word
+        // gives every key its rank, and each entry goes straight to its place.
+        constexpr int RW = (int)(sizeof(NumLds<G, V>) / sizeof(uint2));
+        if (ncolsB <= (int64_t)RW * 32) {
+            uint2 *rw = reinterpret_cast<uint2 *>(&lds);
+            const int nw = (int)((ncolsB + 31) >> 5);
+            for (int i = tid; i < nw; i += G) rw[i] = make_uint2(0u, 0u);
+            __syncthreads();
+            for (int s = tid; s < T; s += G) {
+                const int k = keys[s];
+                if (k != -1) atomicOr(&rw[k >> 5].x, 1u << (k & 31));
+            }
+            __syncthreads();
+            const int S = (nw + G - 1) / G;
+            const int w0 = tid * S;
+            int c = 0;
+            for (int j = 0; j < S; ++j)
+                if (w0 + j < nw) c += __popc(rw[w0 + j].x);
+            int total;
+            int pre = block_excl_scan<G, int>(c, total, rank_ws);
+            for (int j = 0; j < S; ++j)
+                if (w0 + j < nw) {
+                    rw[w0 + j].y = (uint32_t)pre;
+                    pre += __popc(rw[w0 + j].x);
+                }
+            __syncthreads();
+            if (total != expected && tid == 0) atomicOr(&wh->err, ERR_COUNT);
+            for (int s = tid; s < T; s += G) {
+                const int k = keys[s];
+                if (k != -1) {
+                    const uint2 e = rw[k >> 5];
+                    const int r = (int)(e.y + __popc(e.x & ((1u << (k & 31)) - 1u)));
+                    if (r < expected) {
+                        cC[o + r] = k;
+                        vC[o + r] = vals[s];
+                    }
+                }
+            }
+            return;
+        }
+    }
     compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
 }
 
@@ -1203,7 +1258,7 @@ static void num_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const C
                        const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, uint32_t hmul, hipStream_t s) {
     constexpr int U = u_for(G, T / 2 + 1) < 4 ? u_for(G, T / 2 + 1) : 4;
     k_num_hash<G, T, U, SORTED, V><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, (const V *)A.vals, B.rpts, B.cols,
-                                                     (const V *)B.vals, rpts_C, cC, (V *)vC, wh, hmul);
+                                                     (const V *)B.vals, rpts_C, cC, (V *)vC, wh, hmul, B.ncols);
 }
 
 template <bool SORTED, typename V>
