@@ -259,6 +259,8 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
 // column of C (matrices wider than the bitmap are swept in passes of NWORDS*32
 // columns), then the popcount of every 4096-column chunk is kept for the
 // window split of the numeric phase.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <int NWORDS>
 __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__ perm, int64_t perm_off,
                                                      const int32_t *__restrict__ rA,
@@ -269,13 +271,15 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
                                                      int32_t *__restrict__ nnz_row,
                                                      uint32_t *__restrict__ bmap) {
     constexpr int G = 1024;
-    constexpr int NW = G / WAVE;
     constexpr int64_t WIN = (int64_t)NWORDS * 32;
+    constexpr int Q_PER_CHUNK = WORDS_PER_CHUNK / 4;          // 16-byte quads per chunk
     static_assert(NWORDS % WORDS_PER_CHUNK == 0, "bitmap pass must hold whole chunks");
-    __shared__ uint32_t bm[NWORDS];
+    static_assert(Q_PER_CHUNK == 32 && G % Q_PER_CHUNK == 0, "a chunk is half a wave of quads");
+    __shared__ __align__(16) uint32_t bm[NWORDS];
     __shared__ SegLds<G, false, double> sg;
     __shared__ int s_total;
-    const int tid = threadIdx.x, ln = tid & 63, w = tid >> 6;
+    u32x4 *bm4 = reinterpret_cast<u32x4 *>(bm);
+    const int tid = threadIdx.x;
     const int slot = blockIdx.x;
     const int row = perm[perm_off + slot];
     if (tid == 0) s_total = 0;
@@ -284,8 +288,10 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
     for (int pass = 0; pass < npass; ++pass) {
         const int64_t c0 = (int64_t)pass * WIN;
         const uint32_t wcols = (uint32_t)(ncols - c0 < WIN ? ncols - c0 : WIN);
-        const int nw = (int)((wcols + 31) >> 5);
-        for (int i = tid; i < nw; i += G) bm[i] = 0;
+        const int nch = (int)((wcols + CHUNK_COLS - 1) >> CHUNK_SHIFT);
+        const int nq = nch * Q_PER_CHUNK;                    // whole chunks, 16 bytes at a time
+        const int chunk0 = (int)(c0 >> CHUNK_SHIFT);
+        for (int i = tid; i < nq; i += G) bm4[i] = u32x4{0u, 0u, 0u, 0u};
         __syncthreads();
         enum_row<G, U_SEG, false, double>(
             a0, a1, cA, nullptr, sg,
@@ -304,18 +310,15 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
                 }
             });
         __syncthreads();
-        const int nch = (int)((wcols + CHUNK_COLS - 1) >> CHUNK_SHIFT);
-        const int chunk0 = (int)(c0 >> CHUNK_SHIFT);
-        for (int c = w; c < nch; c += NW) {
-            int cw = 0;
-            for (int j = ln; j < WORDS_PER_CHUNK; j += WAVE) {
-                const int wi = c * WORDS_PER_CHUNK + j;
-                if (wi < nw) cw += __popc(bm[wi]);
-            }
-            cw = wave_sum_i32(cw);
-            if (ln == 0) {
-                chunk_cnt[(size_t)slot * nchunks + chunk0 + c] = (uint32_t)cw;
-                atomicAdd(&s_total, cw);
+        // per-chunk counts: a chunk is 32 consecutive quads, i.e. half a wave
+        for (int i = tid; i < nq; i += G) {
+            const u32x4 v = bm4[i];
+            int c = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+#pragma unroll
+            for (int d = 16; d > 0; d >>= 1) c += __shfl_xor(c, d);
+            if ((i & (Q_PER_CHUNK - 1)) == 0) {
+                chunk_cnt[(size_t)slot * nchunks + chunk0 + i / Q_PER_CHUNK] = (uint32_t)c;
+                atomicAdd(&s_total, c);
             }
         }
         __syncthreads();
@@ -323,9 +326,8 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
         // one-pass row that ends up with at most WIN_CAP entries takes a hash
         // table instead and needs none
         if (bmap && (npass > 1 || s_total > WIN_CAP)) {
-            uint32_t *dst = bmap + ((size_t)slot * nchunks + chunk0) * WORDS_PER_CHUNK;
-            for (int i = tid; i < nch * WORDS_PER_CHUNK; i += G)
-                __builtin_nontemporal_store(i < nw ? bm[i] : 0u, &dst[i]);
+            u32x4 *dst = reinterpret_cast<u32x4 *>(bmap + ((size_t)slot * nchunks + chunk0) * WORDS_PER_CHUNK);
+            for (int i = tid; i < nq; i += G) __builtin_nontemporal_store(bm4[i], &dst[i]);
         }
         __syncthreads();
     }
