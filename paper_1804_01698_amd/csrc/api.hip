@@ -371,7 +371,7 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
                 char name[32];
                 snprintf(name, sizeof(name), "sym_hash_%d", SYM_T[b]);
                 HIPCK(timed(pl, name, rows_bytes,
-                            [&] { return launch_sym_bin(b, nr, perm, off.v[b], q.A, q.B, nnz, q.wh, pl->lim.hmul, s); }),
+                            [&] { return launch_sym_bin(b, nr, perm, off.v[b], q.A, q.B, nnz, q.wh, pl->lim.hmul, pl->ncu, s); }),
                       "sym_hash");
             }
         }
@@ -459,7 +459,7 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
             HIPCK(timed(pl, name, bytes,
                         [&] {
                             return launch_num_bin(b, pl->dtype, sorted, nr, perm, q.num_off[b], q.A, q.B, q.rpts_C,
-                                                  cols_C[p], vals_C[p], q.wh, pl->lim.hmul, s);
+                                                  cols_C[p], vals_C[p], q.wh, pl->lim.hmul, pl->ncu, s);
                         }),
                   "num_hash");
         }

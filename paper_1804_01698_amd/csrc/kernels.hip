@@ -217,8 +217,8 @@ __global__ __launch_bounds__(256) void k_num_scatter(int m, const int32_t *__res
 
 // ----------------------------------------------------------------------- symbolic
 
-template <int G, int T, int U>
-__global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm, int64_t perm_off,
+template <int G, int T, int U, bool PERSIST>
+__global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm, int64_t perm_off, unsigned nrows,
                                                 const int32_t *__restrict__ rA,
                                                 const int32_t *__restrict__ cA,
                                                 const int32_t *__restrict__ rB,
@@ -227,31 +227,35 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
     __shared__ __align__(16) int tab[T];
     __shared__ SegLds<G, false, double> sg;
     const int tid = threadIdx.x;
-    const int row = perm[perm_off + blockIdx.x];
-    for (int i = tid; i < T; i += G) tab[i] = -1;
-    __syncthreads();
-    int cnt = 0, ovf = 0;
-    enum_row<G, U, false, double>(
-        rA[row], rA[row + 1], cA, nullptr, sg,
-        [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
-        [&](const int (&q)[U], const bool (&ok)[U], const double (&)[U]) {
-            int col[U];
+    // persistent over the bin's rows, or one row per block (a single trip)
+    for (unsigned it = blockIdx.x; it < (PERSIST ? nrows : blockIdx.x + 1); it += (PERSIST ? gridDim.x : 1)) {
+        const int row = perm[perm_off + it];
+        for (int i = tid; i < T; i += G) tab[i] = -1;
+        __syncthreads();
+        int cnt = 0, ovf = 0;
+        enum_row<G, U, false, double>(
+            rA[row], rA[row + 1], cA, nullptr, sg,
+            [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
+            [&](const int (&q)[U], const bool (&ok)[U], const double (&)[U]) {
+                int col[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = cB[q[u]];                   // q is always a valid index
-                col[u] = ok[u] ? c : 0;
-            }
+                for (int u = 0; u < U; ++u) {
+                    const int c = cB[q[u]];               // q is always a valid index
+                    col[u] = ok[u] ? c : 0;
+                }
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hmul);
-        });
-    __syncthreads();
-    int total;
-    block_excl_scan<G, int>(cnt, total, sg.wsum);
-    if (tid == 0) nnz_row[row] = total;
-    if (ovf) {
-        atomicAdd(&wh->probe_overflow, 1u);
-        atomicOr(&wh->err, ERR_PROBE);
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hmul);
+            });
+        __syncthreads();
+        int total;
+        block_excl_scan<G, int>(cnt, total, sg.wsum);
+        if (tid == 0) nnz_row[row] = total;
+        if (ovf) {
+            atomicAdd(&wh->probe_overflow, 1u);
+            atomicOr(&wh->err, ERR_PROBE);
+        }
+        if constexpr (PERSIST) __syncthreads();           // the table is reused by the next row
     }
 }
 
@@ -619,8 +623,8 @@ struct NumLds {
     uint2 extra[G == 512 ? 1024 : 1];
 };
 
-template <int G, int T, int U, bool SORTED, typename V>
-__global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm, int64_t perm_off,
+template <int G, int T, int U, bool SORTED, typename V, bool PERSIST>
+__global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm, int64_t perm_off, unsigned nrows,
                                                 const int32_t *__restrict__ rA,
                                                 const int32_t *__restrict__ cA,
                                                 const V *__restrict__ vA,
@@ -636,79 +640,84 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
     __shared__ int rank_ws[G / WAVE + 1];
     SegLds<G, true, V> &sg = lds.sg;
     const int tid = threadIdx.x;
-    const int row = perm[perm_off + blockIdx.x];
-    for (int i = tid; i < T; i += G) { keys[i] = -1; vals[i] = V(0); }
-    __syncthreads();
-    int ovf = 0;
-    enum_row<G, U, true, V>(
-        rA[row], rA[row + 1], cA, vA, sg,
-        [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
-        [&](const int (&q)[U], const bool (&ok)[U], const V (&av)[U]) {
-            int col[U];
-            V x[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = cB[q[u]];                   // q is always a valid index
-                const V b = vB[q[u]];
-                col[u] = ok[u] ? c : 0;
-                x[u] = ok[u] ? av[u] * b : V(0);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf, hmul);
-        });
-    __syncthreads();
-    if (ovf) {
-        atomicAdd(&wh->probe_overflow, 1u);
-        atomicOr(&wh->err, ERR_PROBE);
-    }
-    const int64_t o = rpts_C[row];
-    const int expected = (int)(rpts_C[row + 1] - o);
-    if constexpr (SORTED && G >= 512) {
-        // Sorted output of a wide bin by rank instead of a bitonic sort, when
-        // the columns of C fit a bitmap in the (now idle) enumeration LDS:
-        // occupied keys set their bit, an exclusive popcount prefix per word
-        // gives every key its rank, and each entry goes straight to its place.
-        constexpr int RW = (int)(sizeof(NumLds<G, V>) / sizeof(uint2));
-        if (ncolsB <= (int64_t)RW * 32) {
-            uint2 *rw = reinterpret_cast<uint2 *>(&lds);
-            const int nw = (int)((ncolsB + 31) >> 5);
-            for (int i = tid; i < nw; i += G) rw[i] = make_uint2(0u, 0u);
-            __syncthreads();
-            for (int s = tid; s < T; s += G) {
-                const int k = keys[s];
-                if (k != -1) atomicOr(&rw[k >> 5].x, 1u << (k & 31));
-            }
-            __syncthreads();
-            const int S = (nw + G - 1) / G;
-            const int w0 = tid * S;
-            int c = 0;
-            for (int j = 0; j < S; ++j)
-                if (w0 + j < nw) c += __popc(rw[w0 + j].x);
-            int total;
-            int pre = block_excl_scan<G, int>(c, total, rank_ws);
-            for (int j = 0; j < S; ++j)
-                if (w0 + j < nw) {
-                    rw[w0 + j].y = (uint32_t)pre;
-                    pre += __popc(rw[w0 + j].x);
+    // persistent over the bin's rows, or one row per block (a single trip)
+    for (unsigned it = blockIdx.x; it < (PERSIST ? nrows : blockIdx.x + 1); it += (PERSIST ? gridDim.x : 1)) {
+        const int row = perm[perm_off + it];
+        for (int i = tid; i < T; i += G) { keys[i] = -1; vals[i] = V(0); }
+        __syncthreads();
+        int ovf = 0;
+        enum_row<G, U, true, V>(
+            rA[row], rA[row + 1], cA, vA, sg,
+            [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
+            [&](const int (&q)[U], const bool (&ok)[U], const V (&av)[U]) {
+                int col[U];
+                V x[U];
+    #pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = cB[q[u]];                   // q is always a valid index
+                    const V b = vB[q[u]];
+                    col[u] = ok[u] ? c : 0;
+                    x[u] = ok[u] ? av[u] * b : V(0);
                 }
-            __syncthreads();
-            if (total != expected && tid == 0) atomicOr(&wh->err, ERR_COUNT);
-            for (int s = tid; s < T; s += G) {
-                const int k = keys[s];
-                if (k != -1) {
-                    const uint2 e = rw[k >> 5];
-                    const int r = (int)(e.y + __popc(e.x & ((1u << (k & 31)) - 1u)));
-                    if (r < expected) {
-                        cC[o + r] = k;
-                        vC[o + r] = vals[s];
+    #pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf, hmul);
+            });
+        __syncthreads();
+        if (ovf) {
+            atomicAdd(&wh->probe_overflow, 1u);
+            atomicOr(&wh->err, ERR_PROBE);
+        }
+        const int64_t o = rpts_C[row];
+        const int expected = (int)(rpts_C[row + 1] - o);
+        bool ranked = false;
+        if constexpr (SORTED && G >= 512) {
+            // Sorted output of a wide bin by rank instead of a bitonic sort, when
+            // the columns of C fit a bitmap in the (now idle) enumeration LDS:
+            // occupied keys set their bit, an exclusive popcount prefix per word
+            // gives every key its rank, and each entry goes straight to its place.
+            constexpr int RW = (int)(sizeof(NumLds<G, V>) / sizeof(uint2));
+            if (ncolsB <= (int64_t)RW * 32) {
+                uint2 *rw = reinterpret_cast<uint2 *>(&lds);
+                const int nw = (int)((ncolsB + 31) >> 5);
+                for (int i = tid; i < nw; i += G) rw[i] = make_uint2(0u, 0u);
+                __syncthreads();
+                for (int s = tid; s < T; s += G) {
+                    const int k = keys[s];
+                    if (k != -1) atomicOr(&rw[k >> 5].x, 1u << (k & 31));
+                }
+                __syncthreads();
+                const int S = (nw + G - 1) / G;
+                const int w0 = tid * S;
+                int c = 0;
+                for (int j = 0; j < S; ++j)
+                    if (w0 + j < nw) c += __popc(rw[w0 + j].x);
+                int total;
+                int pre = block_excl_scan<G, int>(c, total, rank_ws);
+                for (int j = 0; j < S; ++j)
+                    if (w0 + j < nw) {
+                        rw[w0 + j].y = (uint32_t)pre;
+                        pre += __popc(rw[w0 + j].x);
+                    }
+                __syncthreads();
+                if (total != expected && tid == 0) atomicOr(&wh->err, ERR_COUNT);
+                for (int s = tid; s < T; s += G) {
+                    const int k = keys[s];
+                    if (k != -1) {
+                        const uint2 e = rw[k >> 5];
+                        const int r = (int)(e.y + __popc(e.x & ((1u << (k & 31)) - 1u)));
+                        if (r < expected) {
+                            cC[o + r] = k;
+                            vC[o + r] = vals[s];
+                        }
                     }
                 }
+                ranked = true;
             }
-            return;
         }
+        if (!ranked) compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
+        if constexpr (PERSIST) __syncthreads();               // the table is reused by the next row
     }
-    compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
 }
 
 // Claim of the next window for the block (thread 0 only): windows, sorted by
@@ -1128,6 +1137,14 @@ __global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ s
 
 static inline unsigned grid1(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// Blocks of a kernel that fit on one CU at once (asked of the runtime once).
+template <class K>
+static int blocks_per_cu(K kern, int G) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, G, 0) != hipSuccess || occ < 1) occ = 1;
+    return occ;
+}
+
 hipError_t launch_validate(const CsrDev &a, int *err, hipStream_t s) {
     const unsigned g = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, grid1(std::max(a.nrows, a.nnz), 256)));
     k_validate<<<g, 256, 0, s>>>(a.nrows, a.ncols, a.nnz, a.rpts, a.cols, err);
@@ -1153,24 +1170,28 @@ hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const
 
 template <int G, int T>
 static void sym_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                       const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, hipStream_t s) {
+                       const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, int ncu, hipStream_t s) {
     constexpr int U = u_for(G, T / 2 + 1);
-    k_sym_hash<G, T, U><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, nnz_row, wh, hmul);
+    // wide bins (few blocks per CU) run persistent; narrow ones a block per row
+    constexpr bool P = G >= 512;
+    static const int occ = P ? blocks_per_cu(k_sym_hash<G, T, U, P>, G) : 0;
+    const unsigned grid = P ? (unsigned)std::min<int64_t>(nrows, (int64_t)ncu * occ) : nrows;
+    k_sym_hash<G, T, U, P><<<grid, G, 0, s>>>(perm, off, nrows, A.rpts, A.cols, B.rpts, B.cols, nnz_row, wh, hmul);
 }
 
 hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, hipStream_t s) {
+                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, int ncu, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     switch (bin) {
-        case 1: sym_hash_l<SYM_G[1], SYM_T[1]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
-        case 2: sym_hash_l<SYM_G[2], SYM_T[2]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
-        case 3: sym_hash_l<SYM_G[3], SYM_T[3]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
-        case 4: sym_hash_l<SYM_G[4], SYM_T[4]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
-        case 5: sym_hash_l<SYM_G[5], SYM_T[5]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
-        case 6: sym_hash_l<SYM_G[6], SYM_T[6]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
-        case 7: sym_hash_l<SYM_G[7], SYM_T[7]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
-        case 8: sym_hash_l<SYM_G[8], SYM_T[8]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
-        case 9: sym_hash_l<SYM_G[9], SYM_T[9]>(nrows, perm, off, A, B, nnz_row, wh, hmul, s); break;
+        case 1: sym_hash_l<SYM_G[1], SYM_T[1]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
+        case 2: sym_hash_l<SYM_G[2], SYM_T[2]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
+        case 3: sym_hash_l<SYM_G[3], SYM_T[3]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
+        case 4: sym_hash_l<SYM_G[4], SYM_T[4]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
+        case 5: sym_hash_l<SYM_G[5], SYM_T[5]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
+        case 6: sym_hash_l<SYM_G[6], SYM_T[6]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
+        case 7: sym_hash_l<SYM_G[7], SYM_T[7]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
+        case 8: sym_hash_l<SYM_G[8], SYM_T[8]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
+        case 9: sym_hash_l<SYM_G[9], SYM_T[9]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1257,26 +1278,32 @@ hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &o
 
 template <int G, int T, bool SORTED, typename V>
 static void num_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                       const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, uint32_t hmul, hipStream_t s) {
+                       const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, uint32_t hmul, int ncu,
+                       hipStream_t s) {
     constexpr int U = u_for(G, T / 2 + 1) < 4 ? u_for(G, T / 2 + 1) : 4;
-    k_num_hash<G, T, U, SORTED, V><<<nrows, G, 0, s>>>(perm, off, A.rpts, A.cols, (const V *)A.vals, B.rpts, B.cols,
-                                                     (const V *)B.vals, rpts_C, cC, (V *)vC, wh, hmul, B.ncols);
+    // wide bins (few blocks per CU) run persistent; narrow ones a block per row
+    constexpr bool P = G >= 512;
+    static const int occ = P ? blocks_per_cu(k_num_hash<G, T, U, SORTED, V, P>, G) : 0;
+    const unsigned grid = P ? (unsigned)std::min<int64_t>(nrows, (int64_t)ncu * occ) : nrows;
+    k_num_hash<G, T, U, SORTED, V, P><<<grid, G, 0, s>>>(perm, off, nrows, A.rpts, A.cols, (const V *)A.vals, B.rpts,
+                                                    B.cols, (const V *)B.vals, rpts_C, cC, (V *)vC, wh, hmul,
+                                                    B.ncols);
 }
 
 template <bool SORTED, typename V>
 static hipError_t num_bin_t(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
                             const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh,
-                            uint32_t hmul, hipStream_t s) {
+                            uint32_t hmul, int ncu, hipStream_t s) {
     switch (bin) {
-        case 1: num_hash_l<NUM_G[1], NUM_T[1], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
-        case 2: num_hash_l<NUM_G[2], NUM_T[2], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
-        case 3: num_hash_l<NUM_G[3], NUM_T[3], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
-        case 4: num_hash_l<NUM_G[4], NUM_T[4], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
-        case 5: num_hash_l<NUM_G[5], NUM_T[5], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
-        case 6: num_hash_l<NUM_G[6], NUM_T[6], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
-        case 7: num_hash_l<NUM_G[7], NUM_T[7], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
-        case 8: num_hash_l<NUM_G[8], NUM_T[8], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
-        case 9: num_hash_l<NUM_G[9], NUM_T[9], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s); break;
+        case 1: num_hash_l<NUM_G[1], NUM_T[1], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
+        case 2: num_hash_l<NUM_G[2], NUM_T[2], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
+        case 3: num_hash_l<NUM_G[3], NUM_T[3], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
+        case 4: num_hash_l<NUM_G[4], NUM_T[4], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
+        case 5: num_hash_l<NUM_G[5], NUM_T[5], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
+        case 6: num_hash_l<NUM_G[6], NUM_T[6], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
+        case 7: num_hash_l<NUM_G[7], NUM_T[7], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
+        case 8: num_hash_l<NUM_G[8], NUM_T[8], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
+        case 9: num_hash_l<NUM_G[9], NUM_T[9], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1284,25 +1311,20 @@ static hipError_t num_bin_t(int bin, unsigned nrows, const int32_t *perm, int64_
 
 hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
                           const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
-                          WsHdr *wh, uint32_t hmul, hipStream_t s) {
+                          WsHdr *wh, uint32_t hmul, int ncu, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     if (dtype == 0)
-        return sorted ? num_bin_t<true, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s)
-                      : num_bin_t<false, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s);
-    return sorted ? num_bin_t<true, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s)
-                  : num_bin_t<false, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, s);
+        return sorted ? num_bin_t<true, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s)
+                      : num_bin_t<false, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s);
+    return sorted ? num_bin_t<true, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s)
+                  : num_bin_t<false, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu,
+                                                         s);
 }
 
 __global__ void k_zero_u32n(unsigned *p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
-template <class K>
-static int blocks_per_cu(K kern, int G) {
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, G, 0) != hipSuccess || occ < 1) occ = 1;
-    return occ;
-}
 
 // Windows leave in ascending column order, so sorted and unsorted output share it.
 hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
