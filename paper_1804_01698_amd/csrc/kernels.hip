@@ -397,37 +397,58 @@ __global__ __launch_bounds__(1024) void k_scan_down(const int32_t *__restrict__ 
 // ----------------------------------------------------------------------- windows
 
 // Column windows of the heavy rows.  Greedy split of a row's chunks: a window
-// takes chunks while its LDS footprint fits RANK_BUDGET words (in half words:
-// 256 per chunk for its 128 bit/rank words, 3 per entry for the value word
-// and a half-word staging slot); empty chunks are not opened at a window
-// start.  The windows are laid out sorted by first chunk so that the blocks
-// running side by side read the same column slices of the shared B rows.
+// opens at the first non-empty chunk and takes chunks while its LDS footprint
+// fits RANK_BUDGET words (in half words: 256 per chunk for its 128 bit/rank
+// words, 3 per entry for the value word and a half-word staging slot); its
+// first chunk is always taken.  The windows are laid out sorted by first
+// chunk so that the blocks running side by side read the same column slices
+// of the shared B rows.
 // One wave per heavy row: the row's chunk counts are read 64 at a time
-// (coalesced) and the greedy split runs on wave-uniform state; f(lo, hi, cnt)
-// is called by every lane of the wave for every window.
+// (coalesced) and their footprints prefix-summed across the wave; a window's
+// end is then the first lane whose running footprint overflows (a ballot), so
+// the split costs a few wave operations per window, not a step per chunk.
+// f(lo, hi, cnt) is called by every lane of the wave for every window.
 template <class F>
 __device__ __forceinline__ void wave_windows(const uint32_t *__restrict__ cc, int nchunks, F f) {
+    constexpr int CAP = 2 * RANK_BUDGET;
     const int ln = threadIdx.x & 63;
-    int units = 0, cnt = 0, start = 0;
+    bool open = false;                   // wave-uniform state of the window being built
+    int start = 0, units = 0, cnt = 0;
     for (int t = 0; t < nchunks; t += WAVE) {
-        const int xv = t + ln < nchunks ? (int)cc[t + ln] : 0;
         const int n = min(WAVE, nchunks - t);
-        for (int j = 0; j < n; ++j) {
-            const int x = __builtin_amdgcn_readlane(xv, j);
-            const int c = t + j;
-            if (cnt == 0 && x == 0) { start = c + 1; continue; }
-            const int add = 2 * WORDS_PER_CHUNK + 3 * x;
-            if (units + add > 2 * RANK_BUDGET && cnt > 0) {
-                f(start, c, cnt);
-                start = c;
+        const int x = ln < n ? (int)cc[t + ln] : 0;
+        const int pu = wave_incl_scan<int>(ln < n ? 2 * WORDS_PER_CHUNK + 3 * x : 0);
+        const int px = wave_incl_scan<int>(x);
+        int pos = 0;                     // first chunk of the tile not yet placed
+        while (pos < n) {
+            int first = pos;             // lanes from here on may end the window
+            if (!open) {
+                const uint64_t ne = __ballot(ln >= pos && x > 0);
+                if (ne == 0) break;
+                pos = __ffsll((unsigned long long)ne) - 1;
+                open = true;
+                start = t + pos;
                 units = 0;
                 cnt = 0;
+                first = pos + 1;
             }
-            units += add;
-            cnt += x;
+            const int ub = pos > 0 ? __builtin_amdgcn_readlane(pu, pos - 1) : 0;
+            const int xb = pos > 0 ? __builtin_amdgcn_readlane(px, pos - 1) : 0;
+            const uint64_t over = __ballot(ln >= first && ln < n && units + pu - ub > CAP);
+            if (over == 0) {
+                units += __builtin_amdgcn_readlane(pu, n - 1) - ub;
+                cnt += __builtin_amdgcn_readlane(px, n - 1) - xb;
+                pos = n;
+            } else {
+                const int e = __ffsll((unsigned long long)over) - 1;   // e > pos, or the window spans tiles
+                cnt += (e > 0 ? __builtin_amdgcn_readlane(px, e - 1) : 0) - xb;
+                f(start, t + e, cnt);
+                open = false;
+                pos = e;
+            }
         }
     }
-    if (cnt > 0) f(start, nchunks, cnt);
+    if (open) f(start, nchunks, cnt);
 }
 
 // Blocks of 16 heavy rows (one per wave); window counts per first chunk are
@@ -755,11 +776,14 @@ constexpr int WIN_PRE_WORDS = 3;
 // marked first (one bit per column in LDS), their ranks are the exclusive
 // prefix of the bit counts, and the products are then added straight into a
 // dense array of values indexed by rank: no hashing, no probing, and the
-// window leaves in ascending column order.  The slice of B row k inside the
-// window is two loads from k's chunk index, or the whole row (filtered by
-// column) when the row is short.  When the symbolic phase kept the row's
-// bits, pass 1 is a copy of the window's words instead.  For a row of at most
-// 1024 entries of A each
+// window leaves in ascending column order.  Each product also writes its
+// column at its rank (every product of a column writes the same value), so
+// the output columns need no separate expansion of the bits: the work is
+// spread over the products instead of over words whose bit counts vary from
+// 0 to 32 within a wave.  The slice of B row k inside the window is two loads
+// from k's chunk index, or the whole row (filtered by column) when the row is
+// short.  When the symbolic phase kept the row's bits, pass 1 is a copy of the
+// window's words instead.  For a row of at most 1024 entries of A each
 // thread holds one a_ik and its slice; the next window's item, a_ik and slice
 // are loaded in stages between the current window's passes, so that their
 // latency hides behind loads the window waits for anyway.  Output stores are
@@ -831,6 +855,7 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         const int c0 = ch_lo << CHUNK_SHIFT;
         uint32_t *w32 = reinterpret_cast<uint32_t *>(buf);   // word w: bits w32[2w], rank prefix w32[2w+1]
         V *vals = reinterpret_cast<V *>(buf + nwords);
+        int32_t *stage = reinterpret_cast<int32_t *>(buf + nwords + count);   // columns by rank
         if (bmap && have_pre) {
 #pragma unroll
             for (int k = 0; k < WIN_PRE_WORDS; ++k)
@@ -940,7 +965,10 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
                 if (off < span) {
                     const uint2 e = reinterpret_cast<const uint2 *>(buf)[off >> 5];
                     const uint32_t rank = e.y + __popc(e.x & ((1u << (off & 31)) - 1u));
-                    if (rank < (uint32_t)count) lds_add(&vals[rank], x[u]);
+                    if (rank < (uint32_t)count) {
+                        lds_add(&vals[rank], x[u]);
+                        stage[rank] = col[u];   // the same value from every product of the column
+                    }
                 }
             }
         };
@@ -948,20 +976,7 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         else enum_row<G, U_RANK2, true, V>(it.a0, it.a1, cA, vA, sg, slice, add);
         __syncthreads();
 
-        // columns staged in rank (= ascending column) order, then written out
-        // together with the values in consecutive runs
-        int32_t *stage = reinterpret_cast<int32_t *>(buf + nwords + count);
-        for (int w = tid; w < nwords; w += G) {
-            uint32_t bits = w32[2 * w];
-            uint32_t r = w32[2 * w + 1];
-            while (bits) {
-                const int j = __ffs(bits) - 1;
-                bits &= bits - 1;
-                if (r < (uint32_t)count) stage[r] = c0 + w * 32 + j;
-                ++r;
-            }
-        }
-        __syncthreads();
+        // values and columns leave in consecutive runs
         for (int r = tid; r < count; r += G) {
             __builtin_nontemporal_store(stage[r], &cC[it.out_pos + r]);
             __builtin_nontemporal_store(vals[r], &vC[it.out_pos + r]);
