@@ -215,6 +215,47 @@ __global__ __launch_bounds__(256) void k_num_scatter(int m, const int32_t *__res
     if (b > 0) perm[off.v[b] + s_base[b] + r] = i;
 }
 
+// ----------------------------------------------------------------------- row prefetch
+
+// A row of A as a hash block starts it: its range and, when it has at most G
+// entries, this thread's entry k (a_ik) with the slice [lo, hi) of B row k.
+// Persistent blocks load the next row's entries while the current row's
+// products run, and the slices once they are done, so a row starts without
+// the dependent chain row -> A range -> k -> B row pointers.
+template <typename V>
+struct RowPre {
+    int row, a0, a1, k, lo, hi;
+    V a;
+};
+
+template <int G, bool NUM, typename V>
+__device__ __forceinline__ RowPre<V> row_pre_entry(int row, const int32_t *__restrict__ rA,
+                                                   const int32_t *__restrict__ cA, const V *__restrict__ vA) {
+    RowPre<V> p{row, rA[row], rA[row + 1], -1, 0, 0, V(0)};
+    const int e = p.a0 + (int)threadIdx.x;
+    if (p.a1 - p.a0 <= G && e < p.a1) {
+        p.k = cA[e];
+        if constexpr (NUM) p.a = vA[e];
+    }
+    return p;
+}
+
+template <typename V>
+__device__ __forceinline__ void row_pre_slice(RowPre<V> &p, const int32_t *__restrict__ rB) {
+    if (p.k >= 0) {
+        p.lo = rB[p.k];
+        p.hi = rB[p.k + 1];
+    }
+}
+
+template <int G, bool NUM, typename V>
+__device__ __forceinline__ RowPre<V> row_pre(int row, const int32_t *__restrict__ rA, const int32_t *__restrict__ cA,
+                                             const V *__restrict__ vA, const int32_t *__restrict__ rB) {
+    RowPre<V> p = row_pre_entry<G, NUM, V>(row, rA, cA, vA);
+    row_pre_slice(p, rB);
+    return p;
+}
+
 // ----------------------------------------------------------------------- symbolic
 
 template <int G, int T, int U, bool PERSIST>
@@ -228,26 +269,39 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
     __shared__ SegLds<G, false, double> sg;
     const int tid = threadIdx.x;
     // persistent over the bin's rows, or one row per block (a single trip)
-    for (unsigned it = blockIdx.x; it < (PERSIST ? nrows : blockIdx.x + 1); it += (PERSIST ? gridDim.x : 1)) {
-        const int row = perm[perm_off + it];
+    const unsigned step = PERSIST ? gridDim.x : nrows;
+    unsigned it = blockIdx.x;
+    if (it >= nrows) return;                              // uniform over the block
+    RowPre<double> cur;
+    if constexpr (PERSIST) cur = row_pre<G, false, double>(perm[perm_off + it], rA, cA, nullptr, rB);
+    else cur = RowPre<double>{perm[perm_off + it], 0, 0, -1, 0, 0, 0.0};
+    while (true) {
+        const int row = cur.row;
         for (int i = tid; i < T; i += G) tab[i] = -1;
         __syncthreads();
+        const unsigned nit = it + step;
+        RowPre<double> nxt{};
+        if constexpr (PERSIST)
+            if (nit < nrows) nxt = row_pre_entry<G, false, double>(perm[perm_off + nit], rA, cA, nullptr);
         int cnt = 0, ovf = 0;
-        enum_row<G, U, false, double>(
-            rA[row], rA[row + 1], cA, nullptr, sg,
-            [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
-            [&](const int (&q)[U], const bool (&ok)[U], const double (&)[U]) {
-                int col[U];
+        auto act = [&](const int (&q)[U], const bool (&ok)[U], const double (&)[U]) {
+            int col[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int c = cB[q[u]];               // q is always a valid index
-                    col[u] = ok[u] ? c : 0;
-                }
+            for (int u = 0; u < U; ++u) {
+                const int c = cB[q[u]];                   // q is always a valid index
+                col[u] = ok[u] ? c : 0;
+            }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hmul);
-            });
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hmul);
+        };
+        auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
+        if (PERSIST && cur.a1 - cur.a0 <= G) enum_chunk<G, U, false, double>(cur.lo, cur.hi - cur.lo, 0.0, sg, act);
+        else if (PERSIST) enum_row<G, U, false, double>(cur.a0, cur.a1, cA, nullptr, sg, slice, act);
+        else enum_row<G, U, false, double>(rA[row], rA[row + 1], cA, nullptr, sg, slice, act);
         __syncthreads();
+        if constexpr (PERSIST)
+            if (nit < nrows) row_pre_slice(nxt, rB);
         int total;
         block_excl_scan<G, int>(cnt, total, sg.wsum);
         if (tid == 0) nnz_row[row] = total;
@@ -255,7 +309,10 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
             atomicAdd(&wh->probe_overflow, 1u);
             atomicOr(&wh->err, ERR_PROBE);
         }
-        if constexpr (PERSIST) __syncthreads();           // the table is reused by the next row
+        if (!PERSIST || nit >= nrows) break;
+        __syncthreads();                                  // the table is reused by the next row
+        it = nit;
+        cur = nxt;
     }
 }
 
@@ -278,7 +335,7 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
     constexpr int64_t WIN = (int64_t)NWORDS * 32;
     constexpr int Q_PER_CHUNK = WORDS_PER_CHUNK / 4;          // 16-byte quads per chunk
     static_assert(NWORDS % WORDS_PER_CHUNK == 0, "bitmap pass must hold whole chunks");
-    static_assert(Q_PER_CHUNK == 32 && G % Q_PER_CHUNK == 0, "a chunk is half a wave of quads");
+    static_assert(Q_PER_CHUNK == 32 && G % 4 == 0, "a chunk is counted by four threads of eight quads");
     __shared__ __align__(16) uint32_t bm[NWORDS];
     __shared__ SegLds<G, false, double> sg;
     __shared__ int s_total;
@@ -314,14 +371,20 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
                 }
             });
         __syncthreads();
-        // per-chunk counts: a chunk is 32 consecutive quads, i.e. half a wave
-        for (int i = tid; i < nq; i += G) {
-            const u32x4 v = bm4[i];
-            int c = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+        // per-chunk counts: four threads per chunk of 32 quads, eight quads
+        // each, read in an order rotated by the thread so that the lanes of a
+        // wave fall on different banks
+        for (int t = tid; t < nch * 4; t += G) {
+            int c = 0;
 #pragma unroll
-            for (int d = 16; d > 0; d >>= 1) c += __shfl_xor(c, d);
-            if ((i & (Q_PER_CHUNK - 1)) == 0) {
-                chunk_cnt[(size_t)slot * nchunks + chunk0 + i / Q_PER_CHUNK] = (uint32_t)c;
+            for (int j = 0; j < Q_PER_CHUNK / 4; ++j) {
+                const u32x4 v = bm4[t * (Q_PER_CHUNK / 4) + ((j + t) & (Q_PER_CHUNK / 4 - 1))];
+                c += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+            }
+            c += __shfl_xor(c, 1);
+            c += __shfl_xor(c, 2);
+            if ((t & 3) == 0) {
+                chunk_cnt[(size_t)slot * nchunks + chunk0 + t / 4] = (uint32_t)c;
                 atomicAdd(&s_total, c);
             }
         }
@@ -662,29 +725,43 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
     SegLds<G, true, V> &sg = lds.sg;
     const int tid = threadIdx.x;
     // persistent over the bin's rows, or one row per block (a single trip)
-    for (unsigned it = blockIdx.x; it < (PERSIST ? nrows : blockIdx.x + 1); it += (PERSIST ? gridDim.x : 1)) {
-        const int row = perm[perm_off + it];
+    const unsigned step = PERSIST ? gridDim.x : nrows;
+    unsigned it = blockIdx.x;
+    if (it >= nrows) return;                                  // uniform over the block
+    RowPre<V> cur;
+    if constexpr (PERSIST) cur = row_pre<G, true, V>(perm[perm_off + it], rA, cA, vA, rB);
+    else cur = RowPre<V>{perm[perm_off + it], 0, 0, -1, 0, 0, V(0)};
+    while (true) {
+        const int row = cur.row;
         for (int i = tid; i < T; i += G) { keys[i] = -1; vals[i] = V(0); }
         __syncthreads();
+        // the next row's A entries are loaded while this row's products run
+        const unsigned nit = it + step;
+        RowPre<V> nxt{};
+        if constexpr (PERSIST)
+            if (nit < nrows) nxt = row_pre_entry<G, true, V>(perm[perm_off + nit], rA, cA, vA);
         int ovf = 0;
-        enum_row<G, U, true, V>(
-            rA[row], rA[row + 1], cA, vA, sg,
-            [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
-            [&](const int (&q)[U], const bool (&ok)[U], const V (&av)[U]) {
-                int col[U];
-                V x[U];
-    #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int c = cB[q[u]];                   // q is always a valid index
-                    const V b = vB[q[u]];
-                    col[u] = ok[u] ? c : 0;
-                    x[u] = ok[u] ? av[u] * b : V(0);
-                }
-    #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf, hmul);
-            });
+        auto act = [&](const int (&q)[U], const bool (&ok)[U], const V (&av)[U]) {
+            int col[U];
+            V x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = cB[q[u]];                       // q is always a valid index
+                const V b = vB[q[u]];
+                col[u] = ok[u] ? c : 0;
+                x[u] = ok[u] ? av[u] * b : V(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf, hmul);
+        };
+        auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
+        if (PERSIST && cur.a1 - cur.a0 <= G) enum_chunk<G, U, true, V>(cur.lo, cur.hi - cur.lo, cur.a, sg, act);
+        else if (PERSIST) enum_row<G, U, true, V>(cur.a0, cur.a1, cA, vA, sg, slice, act);
+        else enum_row<G, U, true, V>(rA[row], rA[row + 1], cA, vA, sg, slice, act);
         __syncthreads();
+        if constexpr (PERSIST)
+            if (nit < nrows) row_pre_slice(nxt, rB);          // and then the slices of their B rows
         if (ovf) {
             atomicAdd(&wh->probe_overflow, 1u);
             atomicOr(&wh->err, ERR_PROBE);
@@ -737,7 +814,10 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
             }
         }
         if (!ranked) compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
-        if constexpr (PERSIST) __syncthreads();               // the table is reused by the next row
+        if (!PERSIST || nit >= nrows) break;
+        __syncthreads();                                      // the table is reused by the next row
+        it = nit;
+        cur = nxt;
     }
 }
 
