@@ -364,7 +364,8 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
                             [&] {
                                 return launch_sym_segments(nr, perm, off.v[b], q.A, q.B, q.nchunks,
                                                            q.at<uint32_t>(q.o_chunk), nnz,
-                                                           q.store_bm ? q.at<uint32_t>(q.o_bmap) : nullptr, s);
+                                                           q.store_bm ? q.at<uint32_t>(q.o_bmap) : nullptr,
+                                                           pl->ncu, s);
                             }),
                       "sym_bitmap");
             } else {

@@ -324,6 +324,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <int NWORDS>
 __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__ perm, int64_t perm_off,
+                                                     unsigned nrows,
                                                      const int32_t *__restrict__ rA,
                                                      const int32_t *__restrict__ cA,
                                                      const int32_t *__restrict__ rB,
@@ -341,27 +342,33 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
     __shared__ int s_total;
     u32x4 *bm4 = reinterpret_cast<u32x4 *>(bm);
     const int tid = threadIdx.x;
-    const int slot = blockIdx.x;
-    const int row = perm[perm_off + slot];
-    if (tid == 0) s_total = 0;
-    const int a0 = rA[row], a1 = rA[row + 1];
+    unsigned slot = blockIdx.x;                               // the row's index in the bin
+    if (slot >= nrows) return;                                // uniform over the block
+    // the bitmap is clear at the start of every pass: cleared once here, then
+    // by the last phase that reads it
+    for (int i = tid; i < NWORDS / 4; i += G) bm4[i] = u32x4{0u, 0u, 0u, 0u};
+    RowPre<double> cur = row_pre<G, false, double>(perm[perm_off + slot], rA, cA, nullptr, rB);
     const int npass = (int)((ncols + WIN - 1) / WIN);
-    for (int pass = 0; pass < npass; ++pass) {
-        const int64_t c0 = (int64_t)pass * WIN;
-        const uint32_t wcols = (uint32_t)(ncols - c0 < WIN ? ncols - c0 : WIN);
-        const int nch = (int)((wcols + CHUNK_COLS - 1) >> CHUNK_SHIFT);
-        const int nq = nch * Q_PER_CHUNK;                    // whole chunks, 16 bytes at a time
-        const int chunk0 = (int)(c0 >> CHUNK_SHIFT);
-        for (int i = tid; i < nq; i += G) bm4[i] = u32x4{0u, 0u, 0u, 0u};
+    auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
+    while (true) {
+        const int row = cur.row;
+        if (tid == 0) s_total = 0;
         __syncthreads();
-        enum_row<G, U_SEG, false, double>(
-            a0, a1, cA, nullptr, sg,
-            [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; },
-            [&](const int (&q)[U_SEG], const bool (&ok)[U_SEG], const double (&)[U_SEG]) {
+        // the next row's A entries are loaded while this row's products run
+        const unsigned nslot = slot + gridDim.x;
+        RowPre<double> nxt{};
+        if (nslot < nrows) nxt = row_pre_entry<G, false, double>(perm[perm_off + nslot], rA, cA, nullptr);
+        for (int pass = 0; pass < npass; ++pass) {
+            const int64_t c0 = (int64_t)pass * WIN;
+            const uint32_t wcols = (uint32_t)(ncols - c0 < WIN ? ncols - c0 : WIN);
+            const int nch = (int)((wcols + CHUNK_COLS - 1) >> CHUNK_SHIFT);
+            const int nq = nch * Q_PER_CHUNK;                // whole chunks, 16 bytes at a time
+            const int chunk0 = (int)(c0 >> CHUNK_SHIFT);
+            auto act = [&](const int (&q)[U_SEG], const bool (&ok)[U_SEG], const double (&)[U_SEG]) {
                 int col[U_SEG];
 #pragma unroll
                 for (int u = 0; u < U_SEG; ++u) {
-                    const int c = cB[q[u]];               // q is always a valid index
+                    const int c = cB[q[u]];                   // q is always a valid index
                     col[u] = ok[u] ? c : -1;
                 }
 #pragma unroll
@@ -369,36 +376,48 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
                     const uint32_t off = (uint32_t)((int64_t)col[u] - c0);
                     if (ok[u] && off < wcols) atomicOr(&bm[off >> 5], 1u << (off & 31));
                 }
-            });
-        __syncthreads();
-        // per-chunk counts: four threads per chunk of 32 quads, eight quads
-        // each, read in an order rotated by the thread so that the lanes of a
-        // wave fall on different banks
-        for (int t = tid; t < nch * 4; t += G) {
-            int c = 0;
+            };
+            if (cur.a1 - cur.a0 <= G) enum_chunk<G, U_SEG, false, double>(cur.lo, cur.hi - cur.lo, 0.0, sg, act);
+            else enum_row<G, U_SEG, false, double>(cur.a0, cur.a1, cA, nullptr, sg, slice, act);
+            __syncthreads();
+            // per-chunk counts: four threads per chunk of 32 quads, eight quads
+            // each, read in an order rotated by the thread so that the lanes of
+            // a wave fall on different banks
+            for (int t = tid; t < nch * 4; t += G) {
+                int c = 0;
 #pragma unroll
-            for (int j = 0; j < Q_PER_CHUNK / 4; ++j) {
-                const u32x4 v = bm4[t * (Q_PER_CHUNK / 4) + ((j + t) & (Q_PER_CHUNK / 4 - 1))];
-                c += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+                for (int j = 0; j < Q_PER_CHUNK / 4; ++j) {
+                    const u32x4 v = bm4[t * (Q_PER_CHUNK / 4) + ((j + t) & (Q_PER_CHUNK / 4 - 1))];
+                    c += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+                }
+                c += __shfl_xor(c, 1);
+                c += __shfl_xor(c, 2);
+                if ((t & 3) == 0) {
+                    chunk_cnt[(size_t)slot * nchunks + chunk0 + t / 4] = (uint32_t)c;
+                    atomicAdd(&s_total, c);
+                }
             }
-            c += __shfl_xor(c, 1);
-            c += __shfl_xor(c, 2);
-            if ((t & 3) == 0) {
-                chunk_cnt[(size_t)slot * nchunks + chunk0 + t / 4] = (uint32_t)c;
-                atomicAdd(&s_total, c);
+            __syncthreads();
+            // the row's bits are kept for the numeric windows (whole chunks); a
+            // one-pass row that ends up with at most WIN_CAP entries takes a
+            // hash table instead and needs none.  The bitmap is cleared behind.
+            if (bmap && (npass > 1 || s_total > WIN_CAP)) {
+                u32x4 *dst = reinterpret_cast<u32x4 *>(bmap + ((size_t)slot * nchunks + chunk0) * WORDS_PER_CHUNK);
+                for (int i = tid; i < nq; i += G) {
+                    __builtin_nontemporal_store(bm4[i], &dst[i]);
+                    bm4[i] = u32x4{0u, 0u, 0u, 0u};
+                }
+            } else {
+                for (int i = tid; i < nq; i += G) bm4[i] = u32x4{0u, 0u, 0u, 0u};
             }
+            __syncthreads();
         }
-        __syncthreads();
-        // the row's bits are kept for the numeric windows (whole chunks); a
-        // one-pass row that ends up with at most WIN_CAP entries takes a hash
-        // table instead and needs none
-        if (bmap && (npass > 1 || s_total > WIN_CAP)) {
-            u32x4 *dst = reinterpret_cast<u32x4 *>(bmap + ((size_t)slot * nchunks + chunk0) * WORDS_PER_CHUNK);
-            for (int i = tid; i < nq; i += G) __builtin_nontemporal_store(bm4[i], &dst[i]);
-        }
-        __syncthreads();
+        if (tid == 0) nnz_row[row] = s_total;
+        if (nslot >= nrows) break;
+        row_pre_slice(nxt, rB);
+        slot = nslot;
+        cur = nxt;
     }
-    if (tid == 0) nnz_row[row] = s_total;
 }
 
 // ----------------------------------------------------------------------- scan
@@ -1292,19 +1311,27 @@ hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t 
     return hipGetLastError();
 }
 
+// persistent: a grid of the blocks that fit the CUs at once walks the bin
+template <int W>
+static void sym_bitmap_l(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
+                         int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, int ncu, hipStream_t s) {
+    static const int occ = blocks_per_cu(k_sym_bitmap<W>, 1024);
+    const unsigned grid = (unsigned)std::min<int64_t>(nbm, (int64_t)ncu * occ);
+    k_sym_bitmap<W><<<grid, 1024, 0, s>>>(perm, off, nbm, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks, chunk_cnt,
+                                          nnz_row, bmap);
+}
+
 hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, hipStream_t s) {
+                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, int ncu,
+                               hipStream_t s) {
     if (nbm == 0) return hipSuccess;
     const int64_t need = (B.ncols + 31) / 32;
     if (need <= BM_WORDS_SMALL)
-        k_sym_bitmap<BM_WORDS_SMALL><<<nbm, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks,
-                                                          chunk_cnt, nnz_row, bmap);
+        sym_bitmap_l<BM_WORDS_SMALL>(nbm, perm, off, A, B, nchunks, chunk_cnt, nnz_row, bmap, ncu, s);
     else if (need <= BM_WORDS_MID)
-        k_sym_bitmap<BM_WORDS_MID><<<nbm, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks,
-                                                        chunk_cnt, nnz_row, bmap);
+        sym_bitmap_l<BM_WORDS_MID>(nbm, perm, off, A, B, nchunks, chunk_cnt, nnz_row, bmap, ncu, s);
     else
-        k_sym_bitmap<BM_WORDS_LARGE><<<nbm, 1024, 0, s>>>(perm, off, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks,
-                                                          chunk_cnt, nnz_row, bmap);
+        sym_bitmap_l<BM_WORDS_LARGE>(nbm, perm, off, A, B, nchunks, chunk_cnt, nnz_row, bmap, ncu, s);
     return hipGetLastError();
 }
 
