@@ -43,7 +43,17 @@ WORKLOADS = {
                         "masked product of L*U over A's pattern without forming C, count=sum/2", sorted=None),
     "batch": dict(desc="small stratum of the served stream (n*d^2 <= 2^20): the products of one batch through "
                        "the batched path vs one launch sequence per product", sorted=None),
+    "sweep_density": dict(desc="C=A*A at scale 16, ER (fixed degree) and G500 R-MAT, edge factor 2..64, sorted "
+                               "and unsorted output (the density sweep of Section 5.4)", sorted=None),
+    "sweep_size": dict(desc="C=A*A, ER scale 7..20 and G500 R-MAT scale 7..17, edge factor 16, sorted and "
+                            "unsorted output (the size sweep of Section 5.4)", sorted=None),
+    "tallskinny": dict(desc="C=A*B, A G500 R-MAT scale 18..20 ef 16, B = 2^10..2^16 columns of A drawn at "
+                            "random, sorted and unsorted output (Section 5.5)", sorted=None),
+    "stanza": dict(desc="stanza read probe: stanzas of 2^k consecutive 8-byte words (k = 0..13) from random "
+                        "places of a 4 GiB array (HBM) and of a 64 MiB array (fits the 256 MB Infinity Cache)",
+                   sorted=None),
 }
+SWEEPS = ("sweep_density", "sweep_size", "tallskinny")
 
 
 def log(msg):
@@ -118,6 +128,10 @@ def main():
         return bench_serve(args, sp, dev, *host_serve)
     if args.workload == "batch":
         return bench_batch(args, sp, dev, host_serve[1])
+    if args.workload in SWEEPS:
+        return bench_sweep(args, sp, dev)
+    if args.workload == "stanza":
+        return bench_stanza(args, sp, dev)
 
     t_gen = time.perf_counter()
     inp = make_inputs(args.workload, args.seed, args.sorted_flag)
@@ -350,6 +364,139 @@ def _upload(sp, ops, dev):
     from paper_1804_01698_amd.serve import Request
     return [Request(r.rid, r.arrival_s, sp.DeviceCSR.from_host(a, device=dev), sp.DeviceCSR.from_host(b, device=dev),
                     r.sorted_out) for r, a, b in ops]
+
+
+def _sweep_points(name, seed):
+    """(label, A, B, sorted, params) of a sweep workload, built lazily."""
+    from synth import column_sample, erdos_renyi_fixed_degree, rmat
+    if name == "sweep_density":
+        for fam in ("er", "g500"):
+            for ef in (2, 4, 8, 16, 32, 64):
+                for srt in (False, True):
+                    A = (erdos_renyi_fixed_degree(1 << 16, ef, seed, sorted_rows=srt) if fam == "er"
+                         else rmat(16, ef, seed, sorted_rows=srt))
+                    yield f"{fam} s16 ef{ef} {'sorted' if srt else 'unsorted'}", A, A, srt, dict(
+                        family=fam, scale=16, ef=ef, sorted=srt)
+    elif name == "sweep_size":
+        for fam, scales in (("er", range(7, 21)), ("g500", range(7, 18))):
+            for sc in scales:
+                for srt in (False, True):
+                    A = (erdos_renyi_fixed_degree(1 << sc, 16, seed, sorted_rows=srt) if fam == "er"
+                         else rmat(sc, 16, seed, sorted_rows=srt))
+                    yield f"{fam} s{sc} ef16 {'sorted' if srt else 'unsorted'}", A, A, srt, dict(
+                        family=fam, scale=sc, ef=16, sorted=srt)
+    elif name == "tallskinny":
+        from synth import shuffle_within_rows
+        for sc in (18, 19, 20):
+            A_sorted = rmat(sc, 16, seed)
+            for srt in (False, True):
+                # rmat(..., sorted_rows=False) is this shuffle of the same matrix
+                A = A_sorted if srt else shuffle_within_rows(A_sorted, seed + 2)
+                for lk in (10, 12, 14, 16):
+                    B = column_sample(A, 1 << lk, seed + 3)
+                    yield f"g500 s{sc} x 2^{lk} {'sorted' if srt else 'unsorted'}", A, B, srt, dict(
+                        family="g500", scale=sc, ef=16, k=1 << lk, sorted=srt)
+    else:
+        raise KeyError(name)
+
+
+def bench_sweep(args, sp, dev):
+    """Every point: plan + symbolic + allocation + numeric + free, timed over
+    --steps runs after --warmup; GFLOP/s = 2*flop/t; roofline fraction from the
+    algorithmic bytes 16*flop + 12*nnz(C) + 36*nnz(A) + 40*m over 8 TB/s."""
+    import torch
+    rows = []
+    for label, A, B, srt, params in _sweep_points(args.workload, args.seed):
+        dA = sp.DeviceCSR.from_host(A, device=dev)
+        dB = dA if B is A else sp.DeviceCSR.from_host(B, device=dev)
+
+        def run():
+            p = sp.Plan([dA], [dB], sorted_output=srt)
+            p.symbolic()
+            C = p.numeric()[0]
+            st = p.stats(0)
+            p.close()
+            return C, st
+
+        for _ in range(max(args.warmup, 1)):
+            C, st = run()
+            del C
+        torch.cuda.synchronize()
+        if st["status"] != 0:
+            raise SystemExit(f"device check failed at {label}: {st}")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            C, st = run()
+            del C
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+        flop, nnzc = int(st["flop"]), int(st["nnz_C"])
+        alg = 16.0 * flop + 12.0 * nnzc + 36.0 * A.nnz + 40.0 * A.nrows
+        rows.append(dict(point=label, **params, nnz_A=int(A.nnz), nnz_B=int(B.nnz), flop=flop, nnz_C=nnzc,
+                         ms=round(ms, 4), gflops=round(2.0 * flop / (ms * 1e-3) / 1e9, 2),
+                         roofline_frac=round(alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)))
+        log(f"{label}: {ms:.3f} ms, {rows[-1]['gflops']} GFLOP/s, frac {rows[-1]['roofline_frac']}")
+        del dA, dB
+        torch.cuda.empty_cache()
+    g = [r["gflops"] for r in rows if r["gflops"] > 0]
+    geo = float(np.exp(np.mean(np.log(g)))) if g else 0.0
+    out = {
+        "metric": METRIC, "value": round(geo, 2), "unit": "GFLOP/s (geometric mean over the points)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sum(r["ms"] for r in rows), 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]['desc']}", "points": len(rows),
+                   "seed": args.seed},
+        "points": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_stanza(args, sp, dev):
+    """Stanza bandwidth against stanza length (Section 5's stanza benchmark):
+    bytes of the stanzas read over the kernel time (HIP events), and the same
+    with the 8-byte start of every stanza counted."""
+    import torch
+    rng = np.random.default_rng(args.seed)
+    rows = []
+    for arr_name, nbytes in (("hbm_4GiB", 4 << 30), ("mall_64MiB", 64 << 20)):
+        nwords = nbytes // 8
+        base = torch.ones(nwords, dtype=torch.int64, device=dev)
+        out = torch.empty(2, dtype=torch.int64, device=dev)
+        for lw in range(0, 14):
+            L = 1 << lw
+            nst = max(1 << 12, (1 << 27) >> lw)        # 1 GiB of stanza words per launch
+            starts = torch.from_numpy(rng.integers(0, nwords - L + 1, size=nst, dtype=np.int64)).to(dev)
+            for _ in range(max(args.warmup, 1)):
+                sp.stanza_read(base, starts, lw, out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                sp.stanza_read(base, starts, lw, out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / max(args.steps, 1)
+            got = out.cpu().tolist()
+            if got[0] != nst * L or got[1] != 0:
+                raise SystemExit(f"stanza probe read {got} at lw={lw}, expected {[nst * L, 0]}")
+            data = 8.0 * nst * L
+            rows.append(dict(array=arr_name, stanza_bytes=8 * L, stanzas=nst, ms=round(ms, 4),
+                             gbs=round(data / (ms * 1e-3) / 1e9, 1),
+                             gbs_with_starts=round((data + 8.0 * nst) / (ms * 1e-3) / 1e9, 1)))
+            log(f"{arr_name} stanza {8 * L} B: {rows[-1]['gbs']} GB/s")
+            del starts
+        del base
+        torch.cuda.empty_cache()
+    ref = next(r for r in rows if r["array"] == "hbm_4GiB" and r["stanza_bytes"] == 64)
+    out = {
+        "metric": "stanza read GB/s against stanza length", "value": ref["gbs"], "unit": "GB/s (64-byte stanzas, 4 GiB array)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ref["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"stanza: {WORKLOADS['stanza']['desc']}", "seed": args.seed},
+        "points": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_tri_fused(args, sp, dev, inp):

@@ -243,6 +243,23 @@ int spgemm_masked_product_sum_i64(const spgemm_csr *A, const spgemm_csr *B, cons
  */
 int spgemm_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t stream);
 
+/*
+ * Stanza read probe (the access pattern of B rows, Section 5 on DDR and
+ * MCDRAM: short runs of consecutive words fetched from effectively random
+ * places).  Reads nstanza stanzas of 2^log2_words 8-byte words from the
+ * device array base (nbytes, a multiple of 8, at least 8), stanza s starting
+ * at word start[s] (device array of nstanza int64 word offsets), and writes
+ * the wrap-around sum of every word read to *sum and the number of stanzas
+ * that did not fit the array (skipped, not read) to *skipped; both are device
+ * pointers to 8 bytes owned by the caller.  Consecutive lanes read
+ * consecutive words, so the rate against log2_words traces the bandwidth
+ * between random 8-byte reads and streaming.  0 <= log2_words <=
+ * SPGEMM_STANZA_MAX_LOG2.  Asynchronous on stream; nothing is allocated.
+ */
+enum { SPGEMM_STANZA_MAX_LOG2 = 24 };
+int spgemm_stanza_read(const void *base, size_t nbytes, const int64_t *start, int64_t nstanza, int log2_words,
+                       unsigned long long *sum, unsigned long long *skipped, hipStream_t stream);
+
 /* ---------------------------------------------------------------- batches
  *
  * Many small independent products through one fixed sequence of launches per

@@ -24,11 +24,12 @@ from .binding import (
     masked_product_sum_i64,
     masked_sum_i64,
     spgemm,
+    stanza_read,
     stream_copy,
     triangle_count,
 )
 
 __all__ = [
     "Batch", "BATCH_XMAX", "batch_arena_bytes", "batch_scratch_bytes", "plan_scratch_bytes", "config_ok", "default_config", "DeviceCSR", "Plan", "SpgemmError", "F64", "I64", "SORTED", "VALIDATE", "lib_path",
-    "masked_product_sum_i64", "masked_sum_i64", "spgemm", "stream_copy", "triangle_count",
+    "masked_product_sum_i64", "masked_sum_i64", "spgemm", "stanza_read", "stream_copy", "triangle_count",
 ]

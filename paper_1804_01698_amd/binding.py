@@ -84,6 +84,8 @@ def _load():
                                                   P, P, P]
     lib.spgemm_stream_copy.restype = ctypes.c_int
     lib.spgemm_stream_copy.argtypes = [P, P, ctypes.c_size_t, P]
+    lib.spgemm_stanza_read.restype = ctypes.c_int
+    lib.spgemm_stanza_read.argtypes = [P, ctypes.c_size_t, P, ctypes.c_int64, ctypes.c_int, P, P, P]
     lib.spgemm_batch_scratch_bytes.restype = ctypes.c_size_t
     lib.spgemm_batch_scratch_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr)]
     lib.spgemm_batch_prepare.restype = ctypes.c_int
@@ -465,3 +467,22 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream=None):
     n = min(dst.numel() * dst.element_size(), src.numel() * src.element_size()) // 16 * 16
     _check(_lib.spgemm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n,
                                    _stream_handle(stream)), "spgemm_stream_copy")
+
+
+def stanza_read(base: torch.Tensor, start: torch.Tensor, log2_words: int, out: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """Stanza probe: read the stanzas of 2**log2_words 8-byte words of the
+    device tensor ``base`` that start at the word offsets ``start`` (int64,
+    on the device).  Returns a 2-element int64 device tensor (``out`` if
+    given): the wrap-around sum of the words read and the number of stanzas
+    skipped because they did not fit.  Asynchronous on ``stream``."""
+    if not base.is_contiguous() or not start.is_contiguous() or start.dtype != torch.int64:
+        raise SpgemmError(-1, "stanza_read: contiguous base and int64 starts expected")
+    if out is None:
+        out = torch.empty(2, dtype=torch.int64, device=base.device)
+    nbytes = base.numel() * base.element_size() // 8 * 8
+    _check(_lib.spgemm_stanza_read(ctypes.c_void_p(base.data_ptr()), nbytes, ctypes.c_void_p(start.data_ptr()),
+                                   start.numel(), int(log2_words), ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr() + 8), _stream_handle(stream)),
+           "spgemm_stanza_read")
+    return out

@@ -557,20 +557,22 @@ int spgemm_masked_sum_i64(int64_t nrows, int64_t ncols, const int64_t *rpts_C, c
     return SPGEMM_OK;
 }
 
+// compute units of the current device (256 when the runtime cannot say)
+static int current_ncu() {
+    int devid = 0, n = 0;
+    if (hipGetDevice(&devid) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, devid) == hipSuccess && n > 0)
+        return n;
+    return 256;
+}
+
 int spgemm_masked_product_sum_i64(const spgemm_csr *A, const spgemm_csr *B, const spgemm_csr *M, void *workspace,
                                   int64_t *out, hipStream_t stream) {
     if (!A || !B || !M || !workspace || !out) return SPGEMM_ERR_INVALID_ARG;
     if (!csr_ok(*A) || !csr_ok(*B) || !csr_ok(*M)) return SPGEMM_ERR_INVALID_ARG;
     if (A->ncols != B->nrows || M->nrows != A->nrows || M->ncols != B->ncols) return SPGEMM_ERR_SHAPE;
     const bool ones = !A->vals || !B->vals;
-    int ncu = 256;
-    {
-        int devid = 0, n = 0;
-        if (hipGetDevice(&devid) == hipSuccess &&
-            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, devid) == hipSuccess && n > 0)
-            ncu = n;
-    }
-    HIPCK(launch_masked_product(dev(*A), dev(*B), dev(*M), ones, (unsigned *)workspace, out, ncu, stream),
+    HIPCK(launch_masked_product(dev(*A), dev(*B), dev(*M), ones, (unsigned *)workspace, out, current_ncu(), stream),
           "masked_product");
     return SPGEMM_OK;
 }
@@ -578,6 +580,18 @@ int spgemm_masked_product_sum_i64(const spgemm_csr *A, const spgemm_csr *B, cons
 int spgemm_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t stream) {
     if ((nbytes % 16) != 0 || (nbytes > 0 && (!dst || !src))) return SPGEMM_ERR_INVALID_ARG;
     HIPCK(launch_stream_copy(dst, src, nbytes, stream), "stream_copy");
+    return SPGEMM_OK;
+}
+
+int spgemm_stanza_read(const void *base, size_t nbytes, const int64_t *start, int64_t nstanza, int log2_words,
+                       unsigned long long *sum, unsigned long long *skipped, hipStream_t stream) {
+    if (!base || nbytes < 8 || (nbytes % 8) != 0 || !sum || !skipped) return SPGEMM_ERR_INVALID_ARG;
+    if (log2_words < 0 || log2_words > SPGEMM_STANZA_MAX_LOG2 || nstanza < 0 || (nstanza > 0 && !start))
+        return SPGEMM_ERR_INVALID_ARG;
+    if (nstanza > (INT64_MAX >> SPGEMM_STANZA_MAX_LOG2)) return SPGEMM_ERR_OVERFLOW;
+    HIPCK(launch_stanza_read(base, (int64_t)(nbytes / 8), start, nstanza, log2_words, sum, skipped, current_ncu(),
+                             stream),
+          "stanza_read");
     return SPGEMM_OK;
 }
 

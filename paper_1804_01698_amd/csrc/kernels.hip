@@ -1247,6 +1247,56 @@ __global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ s
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
+// ----------------------------------------------------------------------- stanza probe
+
+// Reads nst stanzas of 2^lw 8-byte words, stanza s starting at word start[s]
+// of base (nwords long), and adds every word read into *sum (wrap-around;
+// one atomic per block).  Consecutive lanes take consecutive words of a
+// stanza, then of the next one, so a short stanza costs its own length plus
+// the read of its start, as a row of B costs an SpGEMM.  A stanza that does
+// not fit the array is skipped and counted in *skipped.
+__global__ __launch_bounds__(256) void k_stanza_read(const unsigned long long *__restrict__ base, int64_t nwords,
+                                                     const int64_t *__restrict__ start, int64_t nst, int lw,
+                                                     unsigned long long *sum, unsigned long long *skipped) {
+    __shared__ unsigned long long s_part[256 / WAVE];
+    const int64_t total = nst << lw;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t wmask = ((int64_t)1 << lw) - 1;
+    constexpr int U = 8;                                      // loads in flight per lane
+    unsigned long long acc = 0, bad = 0;
+    for (int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x; i0 < total; i0 += stride * U) {
+        int64_t st[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * stride;
+            st[u] = i < total ? start[i >> lw] : -1;
+        }
+        unsigned long long v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * stride;
+            const bool fits = st[u] >= 0 && st[u] <= nwords - (wmask + 1);
+            // every lane loads (word 0 when its stanza does not fit) so that the
+            // U loads leave together; the value is dropped afterwards
+            const unsigned long long x = __builtin_nontemporal_load(&base[fits ? st[u] + (i & wmask) : 0]);
+            v[u] = fits ? x : 0ull;
+            bad += (i < total && !fits && (i & wmask) == 0) ? 1ull : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += v[u];
+    }
+    acc = wave_sum_u64(acc);
+    bad = wave_sum_u64(bad);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 256 / WAVE; ++w) t += s_part[w];
+        atomicAdd(sum, t);
+    }
+    if ((threadIdx.x & 63) == 0 && bad) atomicAdd(skipped, bad);
+}
+
 // ======================================================================= launchers
 
 static inline unsigned grid1(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -1508,6 +1558,17 @@ hipError_t launch_masked_sum(int64_t m, int64_t ncols, const int64_t *rC, const 
     if (m > 0)
         k_masked_sum<<<(unsigned)m, 256, 0, s>>>(m, ncols, rC, cC, (const unsigned long long *)vC, M.rpts, M.cols,
                                                  (unsigned long long *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stanza_read(const void *base, int64_t nwords, const int64_t *start, int64_t nst, int lw,
+                              unsigned long long *sum, unsigned long long *skipped, int ncu, hipStream_t s) {
+    k_zero_u64<<<1, 1, 0, s>>>(sum);
+    k_zero_u64<<<1, 1, 0, s>>>(skipped);
+    const int64_t total = nst << lw;
+    if (total == 0) return hipGetLastError();
+    const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, (int64_t)ncu * 32);
+    k_stanza_read<<<g, 256, 0, s>>>((const unsigned long long *)base, nwords, start, nst, lw, sum, skipped);
     return hipGetLastError();
 }
 

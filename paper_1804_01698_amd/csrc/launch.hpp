@@ -57,5 +57,7 @@ hipError_t launch_masked_product(const CsrDev &A, const CsrDev &B, const CsrDev 
 hipError_t launch_masked_sum(int64_t m, int64_t ncols, const int64_t *rC, const int32_t *cC, const int64_t *vC,
                              const CsrDev &M, int64_t *out, hipStream_t s);
 hipError_t launch_stream_copy(void *dst, const void *src, size_t nbytes, hipStream_t s);
+hipError_t launch_stanza_read(const void *base, int64_t nwords, const int64_t *start, int64_t nst, int lw,
+                              unsigned long long *sum, unsigned long long *skipped, int ncu, hipStream_t s);
 
 }  // namespace spg

@@ -13,6 +13,7 @@ from .generators import (
     symmetric_rmat_graph,
     triangle_inputs,
     bfs_frontier,
+    column_sample,
     identity,
     permutation_matrix,
     random_sparse,
@@ -27,6 +28,6 @@ from .generators import (
 __all__ = [
     "CSR", "to_dense", "from_dense", "transpose", "shuffle_within_rows", "sort_within_rows", "validate",
     "erdos_renyi_fixed_degree", "rmat", "rmat_edges", "symmetric_rmat_graph", "triangle_inputs",
-    "bfs_frontier", "identity", "permutation_matrix", "random_sparse", "with_values",
+    "bfs_frontier", "column_sample", "identity", "permutation_matrix", "random_sparse", "with_values",
     "ServingRequest", "serving_stream", "serving_request_operands", "WORKLOADS", "workload",
 ]

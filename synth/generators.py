@@ -152,6 +152,23 @@ def triangle_inputs(a: CSR, degree_order: bool = False):
     return a, part(lo), part(up)
 
 
+def column_sample(a: CSR, k: int, seed: int) -> CSR:
+    """Tall-skinny operand of Section 5.5: k distinct columns of ``a`` drawn
+    uniformly (seeded), kept in ascending order and renumbered 0..k-1, with
+    their entries and values; the row order of ``a`` is kept."""
+    if not 0 < k <= a.ncols:
+        raise ValueError("0 < k <= ncols required")
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(a.ncols, size=k, replace=False))
+    new_id = np.full(a.ncols, -1, dtype=np.int64)
+    new_id[pick] = np.arange(k)
+    nc = new_id[a.cols.astype(np.int64)]
+    keep = nc >= 0
+    rows = a.row_ids()[keep]
+    vals = None if a.vals is None else a.vals[keep]
+    return CSR(a.nrows, k, _rpts_from_rows(a.nrows, rows), nc[keep].astype(np.int32), vals)
+
+
 def bfs_frontier(n: int, nsources: int, seed: int) -> CSR:
     """n x nsources frontier stack: one nonzero per column, uniform row, value in {1..1000}."""
     rng = np.random.default_rng(seed)

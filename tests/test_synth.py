@@ -2,9 +2,10 @@
 import math
 
 import numpy as np
+import pytest
 
-from synth import (bfs_frontier, erdos_renyi_fixed_degree, rmat, serving_request_operands,
-                   serving_stream, shuffle_within_rows, symmetric_rmat_graph, transpose,
+from synth import (bfs_frontier, column_sample, erdos_renyi_fixed_degree, rmat, serving_request_operands,
+                   serving_stream, shuffle_within_rows, symmetric_rmat_graph, to_dense, transpose,
                    triangle_inputs, validate)
 
 
@@ -83,3 +84,31 @@ def test_serving_stream():
         validate(a, allow_duplicates=False)
         validate(b)
         assert a.shape == b.shape == (r.n, r.n)
+
+
+def test_column_sample():
+    # tall-skinny operand (Section 5.5): every column of B is one column of A,
+    # the picked columns are distinct and kept in ascending order; A's random
+    # FP64 values make its non-empty columns unique, so each is located exactly
+    a = rmat(7, 8, 5)
+    da = to_dense(a)
+    k = 40
+    b = column_sample(a, k, 11)
+    assert b.shape == (a.nrows, k)
+    validate(b)
+    db = to_dense(b)
+    src = []
+    n_empty = 0
+    for t in range(k):
+        if not db[:, t].any():
+            n_empty += 1
+            continue
+        hits = [j for j in range(a.ncols) if np.array_equal(db[:, t], da[:, j])]
+        assert len(hits) == 1, f"column {t} of B is not exactly one column of A"
+        src.append(hits[0])
+    assert src == sorted(src) and len(set(src)) == len(src)
+    assert n_empty <= int((~da.any(axis=0)).sum())
+    b2 = column_sample(a, k, 11)
+    assert np.array_equal(b.cols, b2.cols) and np.array_equal(b.rpts, b2.rpts)
+    with pytest.raises(ValueError):
+        column_sample(a, a.ncols + 1, 1)
