@@ -717,9 +717,15 @@ __global__ __launch_bounds__(256) void k_gather_vals(int64_t n, const int32_t *_
 
 // ----------------------------------------------------------------------- numeric
 
+// Column passes of the rank sort of a wide bin before it falls back to bitonic
+// sorting: a pass reads the whole table, so the limit grows with the table
+// (measured at 2^20 columns: 13 passes beat the bitonic network for 11264
+// slots and lose to it for 8192).
+__host__ __device__ constexpr int rank_passes(int T) { return T / 768 > 1 ? T / 768 : 1; }
+
 // LDS of a numeric hash block besides its table: the enumeration state, and
 // (512-thread bins) extra words so that the idle enumeration LDS plus them can
-// hold a rank bitmap of 64 K columns for sorted output.
+// hold a rank bitmap of 64 K columns per pass for sorted output.
 template <int G, typename V>
 struct NumLds {
     SegLds<G, true, V> sg;
@@ -789,46 +795,60 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
         const int expected = (int)(rpts_C[row + 1] - o);
         bool ranked = false;
         if constexpr (SORTED && G >= 512) {
-            // Sorted output of a wide bin by rank instead of a bitonic sort, when
-            // the columns of C fit a bitmap in the (now idle) enumeration LDS:
-            // occupied keys set their bit, an exclusive popcount prefix per word
-            // gives every key its rank, and each entry goes straight to its place.
+            // Sorted output of a wide bin by rank instead of a bitonic sort: the
+            // columns of C are swept in passes of as many columns as a bitmap in
+            // the (now idle) enumeration LDS holds; in a pass, the keys inside
+            // it set their bit, an exclusive popcount prefix per word plus the
+            // keys of the earlier passes gives each its rank, and every entry
+            // goes straight to its place.  Up to rank_passes(T) passes; wider
+            // matrices sort by bitonic networks.
             constexpr int RW = (int)(sizeof(NumLds<G, V>) / sizeof(uint2));
-            if (ncolsB <= (int64_t)RW * 32) {
+            constexpr int64_t PW = (int64_t)RW * 32;
+            const int npass = (int)((ncolsB + PW - 1) / PW);
+            if (npass <= rank_passes(T)) {
                 uint2 *rw = reinterpret_cast<uint2 *>(&lds);
-                const int nw = (int)((ncolsB + 31) >> 5);
-                for (int i = tid; i < nw; i += G) rw[i] = make_uint2(0u, 0u);
-                __syncthreads();
-                for (int s = tid; s < T; s += G) {
-                    const int k = keys[s];
-                    if (k != -1) atomicOr(&rw[k >> 5].x, 1u << (k & 31));
-                }
-                __syncthreads();
-                const int S = (nw + G - 1) / G;
-                const int w0 = tid * S;
-                int c = 0;
-                for (int j = 0; j < S; ++j)
-                    if (w0 + j < nw) c += __popc(rw[w0 + j].x);
-                int total;
-                int pre = block_excl_scan<G, int>(c, total, rank_ws);
-                for (int j = 0; j < S; ++j)
-                    if (w0 + j < nw) {
-                        rw[w0 + j].y = (uint32_t)pre;
-                        pre += __popc(rw[w0 + j].x);
+                int base = 0;
+                for (int ps = 0; ps < npass; ++ps) {
+                    const int c0 = (int)(ps * PW);
+                    const int64_t span = ncolsB - c0 < PW ? ncolsB - c0 : PW;
+                    const int nw = (int)((span + 31) >> 5);
+                    for (int i = tid; i < nw; i += G) rw[i] = make_uint2(0u, 0u);
+                    __syncthreads();
+                    for (int s = tid; s < T; s += G) {
+                        const int k = keys[s];
+                        const uint32_t off = (uint32_t)(k - c0);
+                        if (k != -1 && off < (uint32_t)span) atomicOr(&rw[off >> 5].x, 1u << (off & 31));
                     }
-                __syncthreads();
-                if (total != expected && tid == 0) atomicOr(&wh->err, ERR_COUNT);
-                for (int s = tid; s < T; s += G) {
-                    const int k = keys[s];
-                    if (k != -1) {
-                        const uint2 e = rw[k >> 5];
-                        const int r = (int)(e.y + __popc(e.x & ((1u << (k & 31)) - 1u)));
-                        if (r < expected) {
-                            cC[o + r] = k;
-                            vC[o + r] = vals[s];
+                    __syncthreads();
+                    const int S = (nw + G - 1) / G;
+                    const int w0 = tid * S;
+                    int c = 0;
+                    for (int j = 0; j < S; ++j)
+                        if (w0 + j < nw) c += __popc(rw[w0 + j].x);
+                    int total;
+                    int pre = base + block_excl_scan<G, int>(c, total, rank_ws);
+                    for (int j = 0; j < S; ++j)
+                        if (w0 + j < nw) {
+                            rw[w0 + j].y = (uint32_t)pre;
+                            pre += __popc(rw[w0 + j].x);
+                        }
+                    __syncthreads();
+                    for (int s = tid; s < T; s += G) {
+                        const int k = keys[s];
+                        const uint32_t off = (uint32_t)(k - c0);
+                        if (k != -1 && off < (uint32_t)span) {
+                            const uint2 e = rw[off >> 5];
+                            const int r = (int)(e.y + __popc(e.x & ((1u << (off & 31)) - 1u)));
+                            if (r < expected) {
+                                cC[o + r] = k;
+                                vC[o + r] = vals[s];
+                            }
                         }
                     }
+                    base += total;
+                    __syncthreads();                          // the bitmap is reused by the next pass
                 }
+                if (base != expected && tid == 0) atomicOr(&wh->err, ERR_COUNT);
                 ranked = true;
             }
         }

@@ -316,3 +316,22 @@ def test_sampled_rows_api(sp):
     rows = np.unique(np.concatenate([np.argsort(f)[-50:], np.random.default_rng(0).choice(A.nrows, 200)]))
     ref = oracle.spgemm(A, A, sorted_output=False, rows=rows)
     assert_rows_match(C, ref, rows, False)
+
+
+def test_sorted_wide_bins_rank_passes(sp):
+    # rows of the 512- and 1024-thread bins with their columns spread over
+    # 300,000 columns: sorted output ranks them in several column passes
+    _note("case sorted_wide_bins_rank_passes")
+    rng = np.random.default_rng(21)
+    n, ncols = 4000, 300000
+    degs = np.repeat([300, 800, 1500, 2000], 8)
+    rows = [np.sort(rng.choice(n, size=d, replace=False)) for d in degs]
+    rp = np.zeros(len(degs) + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(degs)
+    A = with_values(CSR(len(degs), n, rp, np.concatenate(rows).astype(np.int32), None), 3, "f64")
+    bcols = np.concatenate([np.sort(rng.choice(ncols, size=3, replace=False)) for _ in range(n)])
+    B = with_values(CSR(n, ncols, np.arange(0, 3 * n + 1, 3, dtype=np.int64), bcols.astype(np.int32), None),
+                    4, "f64")
+    for srt in (True, False):
+        C = _run(sp, shuffle_within_rows(A, 5), B, srt)
+        assert_matches(C, oracle.spgemm(A, B, sorted_output=srt), srt)
