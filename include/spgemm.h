@@ -122,13 +122,18 @@ size_t spgemm_plan_scratch_bytes(int nprod, const spgemm_csr *A);
  * table's size (a fuller table still works, with longer probes), and the
  * ninth must be 8448 (rows above it take the heavy-row path).  hash_mul is
  * the odd multiplier of the hash; 0 sends every key to the first bucket (a
- * worst case, for tests).  The defaults (spgemm_config_default) fill each
- * table at most half.
+ * worst case, for tests).  bucket_slots (4, 8 or 16) is the width of the
+ * tables' buckets: a key's bucket is scanned 4 slots (one 16-byte LDS load)
+ * at a time, front to back, and a full bucket passes the probe to the next;
+ * 8 and 16 are the wider chunks of the HashVector variant (Section 4.2.2).
+ * The defaults (spgemm_config_default) fill each table at most half and use
+ * 4-slot buckets.
  */
 typedef struct {
     uint32_t hash_mul;
     int32_t sym_max[9];
     int32_t num_max[9];
+    uint32_t bucket_slots;
 } spgemm_config;
 
 /* The default configuration. */

@@ -1,4 +1,4 @@
-"""Per-device tuning of the plan configuration (hash multiplier, bin limits).
+"""Per-device tuning of the plan configuration (hash multiplier, bin limits, bucket width).
 
 The paper's recipe (Section 5.7, Table 4) picks the SpGEMM variant by input
 class -- uniform or skewed pattern, sparse (edge factor <= 8) or dense,
@@ -6,7 +6,9 @@ sorted or unsorted output -- and its cost analysis (Section 4.3, Eq. 2)
 prices the hash variant at flop*c + sum_i nnz(c_i) log nnz(c_i), c being the
 mean number of probes per insertion.  Here the same two ideas choose, per
 input class, how full each bin's LDS table may get (a fuller table leaves
-room for more blocks per CU but raises c) and the hash multiplier:
+room for more blocks per CU but raises c), the hash multiplier and the
+bucket width of the tables (4 slots, or the 8- and 16-slot chunks of the
+HashVector variant, Section 4.2.2):
 
 1. candidates: one load limit for the symbolic and one for the numeric
    tables (a fraction of every bin's table), times a few odd multipliers;
@@ -15,7 +17,8 @@ room for more blocks per CU but raises c) and the hash multiplier:
    sum_i flop_i * c(load_i) + table slots initialised and scanned
    + the sort term when output is sorted, with c(load) the expected probes
    of linear probing (Knuth) at the row's actual table load;
-3. the best-ranked candidates (and the defaults) are timed end to end
+3. the best-ranked candidates (and the defaults), and the best-ranked one
+   and the defaults with 8- and 16-slot buckets, are timed end to end
    through the library; the fastest per class is stored in a JSON file keyed
    by device name and CU count.
 
@@ -36,6 +39,7 @@ NUM_TABLE = [64, 128, 256, 512, 1024, 2048, 4096, 8192, 11264]
 HEAVY = 8448
 LOADS = (0.25, 0.5, 0.75, 1.0)
 HASH_MULS = (2654435761, 0x85EBCA6B, 0xCC9E2D51)
+BUCKETS = (4, 8, 16)       # slots per bucket: 4, and the HashVector-style 8 and 16 (Section 4.2.2)
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED_DIR = os.path.join(HERE, "tuned")
 
@@ -67,9 +71,9 @@ def limits_for(load: float, table: Sequence[int]) -> List[int]:
     return out
 
 
-def make_config(sym_load: float, num_load: float, hash_mul: int) -> dict:
+def make_config(sym_load: float, num_load: float, hash_mul: int, bucket_slots: int = 4) -> dict:
     return {"hash_mul": int(hash_mul), "sym_max": limits_for(sym_load, SYM_TABLE),
-            "num_max": limits_for(num_load, NUM_TABLE)}
+            "num_max": limits_for(num_load, NUM_TABLE), "bucket_slots": int(bucket_slots)}
 
 
 # ---------------------------------------------------------------- prior (Eq. 2)
@@ -156,7 +160,11 @@ def tune_class(sp, A, B, sorted_output: bool, top: int = 6, reps: int = 3) -> di
                 cfg = make_config(sl, nl, hm)
                 cands.append((prior_cost(flop, key, nnz, cfg, sorted_output), cfg))
     cands.sort(key=lambda c: c[0])
-    timed = [(None, default)] + [c for c in cands[:top]]
+    # the bucket width is an arm the prior does not price: the defaults and the
+    # best-ranked candidate are also timed with the 8- and 16-slot chunks
+    arms = [(cands[0][0], dict(cands[0][1], bucket_slots=w)) for w in BUCKETS[1:]]
+    arms += [(None, dict(default, bucket_slots=w)) for w in BUCKETS[1:]]
+    timed = [(None, default)] + [c for c in cands[:top]] + arms
     results = []
     for prior, cfg in timed:
         ms = _time_product(sp, dA, dB, sorted_output, cfg, reps) * 1e3

@@ -38,7 +38,8 @@ class _Stats(ctypes.Structure):
 
 
 class _Config(ctypes.Structure):
-    _fields_ = [("hash_mul", ctypes.c_uint32), ("sym_max", ctypes.c_int32 * 9), ("num_max", ctypes.c_int32 * 9)]
+    _fields_ = [("hash_mul", ctypes.c_uint32), ("sym_max", ctypes.c_int32 * 9), ("num_max", ctypes.c_int32 * 9),
+                ("bucket_slots", ctypes.c_uint32)]
 
 
 class _KTime(ctypes.Structure):
@@ -164,10 +165,11 @@ def _dtype_code(A: DeviceCSR, B: DeviceCSR) -> int:
 
 def default_config() -> dict:
     """The library's default plan configuration as a dict
-    {hash_mul, sym_max[9], num_max[9]} (see spgemm_config)."""
+    {hash_mul, sym_max[9], num_max[9], bucket_slots} (see spgemm_config)."""
     c = _Config()
     _lib.spgemm_config_default(ctypes.byref(c))
-    return {"hash_mul": int(c.hash_mul), "sym_max": list(c.sym_max), "num_max": list(c.num_max)}
+    return {"hash_mul": int(c.hash_mul), "sym_max": list(c.sym_max), "num_max": list(c.num_max),
+            "bucket_slots": int(c.bucket_slots)}
 
 
 def _config_struct(cfg: Optional[dict]) -> Optional[_Config]:
@@ -178,6 +180,7 @@ def _config_struct(cfg: Optional[dict]) -> Optional[_Config]:
     for i in range(9):
         c.sym_max[i] = int(cfg["sym_max"][i])
         c.num_max[i] = int(cfg["num_max"][i])
+    c.bucket_slots = int(cfg.get("bucket_slots", 4))
     return c
 
 

@@ -131,7 +131,9 @@ bool limits_from(const spgemm_config *cfg, BinLimits *L) {
         L->num[b] = n;
     }
     if (L->sym[9] != WIN_CAP || L->num[9] != WIN_CAP) return false;
+    if (cfg->bucket_slots != 4 && cfg->bucket_slots != 8 && cfg->bucket_slots != 16) return false;
     L->hmul = cfg->hash_mul;
+    L->bq = cfg->bucket_slots / 4;
     return true;
 }
 
@@ -174,6 +176,7 @@ const char *spgemm_strerror(int status) {
 void spgemm_config_default(spgemm_config *cfg) {
     if (!cfg) return;
     cfg->hash_mul = HASH_MUL_DEFAULT;
+    cfg->bucket_slots = 4;
     for (int b = 1; b <= 9; ++b) {
         cfg->sym_max[b - 1] = (int32_t)SYM_XMAX[b];
         cfg->num_max[b - 1] = (int32_t)NUM_XMAX[b];
@@ -372,7 +375,7 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
                 char name[32];
                 snprintf(name, sizeof(name), "sym_hash_%d", SYM_T[b]);
                 HIPCK(timed(pl, name, rows_bytes,
-                            [&] { return launch_sym_bin(b, nr, perm, off.v[b], q.A, q.B, nnz, q.wh, pl->lim.hmul, pl->ncu, s); }),
+                            [&] { return launch_sym_bin(b, nr, perm, off.v[b], q.A, q.B, nnz, q.wh, HashCfg{pl->lim.hmul, pl->lim.bq}, pl->ncu, s); }),
                       "sym_hash");
             }
         }
@@ -460,7 +463,7 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
             HIPCK(timed(pl, name, bytes,
                         [&] {
                             return launch_num_bin(b, pl->dtype, sorted, nr, perm, q.num_off[b], q.A, q.B, q.rpts_C,
-                                                  cols_C[p], vals_C[p], q.wh, pl->lim.hmul, pl->ncu, s);
+                                                  cols_C[p], vals_C[p], q.wh, HashCfg{pl->lim.hmul, pl->lim.bq}, pl->ncu, s);
                         }),
                   "num_hash");
         }

@@ -51,13 +51,21 @@ constexpr int64_t NUM_XMAX[NNB] = {0, 32, 64, 128, 256, 512, 1024, 2048, 4096, W
 // numeric phase rows with num[b-1] < nnz(c_i) <= num[b].  A limit never
 // exceeds its bin's table size (so a probe always finds room); bin 9 ends at
 // WIN_CAP in both phases (the heavy-row boundary is structural).  hmul is
-// the odd multiplier of the column hash.
+// the odd multiplier of the column hash, bq the 4-slot quads per bucket of
+// the LDS tables (1: 4-slot buckets; 2 or 4: the wider chunks of the
+// paper's HashVector, Section 4.2.2).
 constexpr uint32_t HASH_MUL_DEFAULT = 2654435761u;
 struct BinLimits {
     int64_t sym[NSB];
     int64_t num[NNB];
     uint32_t hmul;
-    uint32_t pad;
+    uint32_t bq;
+};
+
+// What a hash kernel needs of the configuration.
+struct HashCfg {
+    uint32_t mul;   // odd multiplier of the column hash
+    uint32_t bq;    // 4-slot quads per bucket: 1, 2 or 4
 };
 
 __host__ __device__ inline BinLimits default_limits() {
@@ -65,6 +73,7 @@ __host__ __device__ inline BinLimits default_limits() {
     for (int b = 0; b < NSB; ++b) L.sym[b] = SYM_XMAX[b];
     for (int b = 0; b < NNB; ++b) L.num[b] = NUM_XMAX[b];
     L.hmul = HASH_MUL_DEFAULT;
+    L.bq = 1;
     return L;
 }
 

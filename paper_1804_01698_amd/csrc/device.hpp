@@ -165,28 +165,44 @@ __device__ __forceinline__ int bucket_pick(int4 k, int key, bool &empty_hit) {
 }
 
 // Insert key (and with NUM add x to its value); returns 1 if the key is new.
-// A probe that runs past every bucket without room sets ovf and gives up.
-template <bool NUM, typename V>
+// A bucket is bq consecutive quads (4 slots each, one 16-byte LDS load): the
+// quads of the key's bucket are read front to back, a quad holding the key or
+// an empty slot ends the probe (slots, and then quads, fill from the front,
+// so a key is never behind an empty slot), and a full bucket sends the probe
+// to the next bucket.  bq = 1 is the 4-slot bucket; bq = 2 or 4 the 8- or
+// 16-slot chunk of the paper's HashVector (Section 4.2.2), which trades a
+// longer scan of a busy bucket for fewer jumps to the next one.  A probe
+// that runs past every bucket without room sets ovf and gives up.
+// FIXED_BQ > 0 fixes bq at compile time (the default 4-slot buckets compile
+// to the plain one-quad probe).
+template <bool NUM, typename V, int FIXED_BQ = 0>
 __device__ __forceinline__ int bkt_insert(int *keys, V *vals, uint32_t T, int key, V x, int &ovf,
-                                          uint32_t mul = HASH_MUL_DEFAULT) {
-    const uint32_t NB = T / BKT;
+                                          uint32_t mul = HASH_MUL_DEFAULT, uint32_t bq_rt = 1) {
+    const uint32_t bq = FIXED_BQ > 0 ? (uint32_t)FIXED_BQ : bq_rt;
+    const uint32_t W = BKT * bq;                   // slots per bucket
+    const uint32_t NB = T / W;
     uint32_t b = hash_slot(key, NB, mul);
-    for (uint32_t it = 0; it < NB + T; ++it) {
-        __asm__ __volatile__("" ::: "memory");   // re-read the bucket every round
-        const int4 k = lds_load4(&keys[b * BKT]);
+    uint32_t q = 0;                                // quad of the bucket being read
+    for (uint32_t it = 0; it < T / BKT + T; ++it) {
+        __asm__ __volatile__("" ::: "memory");   // re-read the quad every round
+        const uint32_t base = b * W + q * BKT;
+        const int4 k = lds_load4(&keys[base]);
         bool e;
         const int j = bucket_pick(k, key, e);
-        if (j < 0) {
-            b = (b + 1 == NB) ? 0u : b + 1;
+        if (j < 0) {                               // quad full without the key
+            if (++q == bq) {
+                q = 0;
+                b = (b + 1 == NB) ? 0u : b + 1;
+            }
             continue;
         }
         int added = 0;
         if (e) {
-            const int old = atomicCAS(&keys[b * BKT + j], -1, key);
-            if (old != -1 && old != key) continue;    // lost the slot: look at this bucket again
+            const int old = atomicCAS(&keys[base + j], -1, key);
+            if (old != -1 && old != key) continue;    // lost the slot: look at this quad again
             added = old == -1;
         }
-        if constexpr (NUM) lds_add(&vals[b * BKT + j], x);
+        if constexpr (NUM) lds_add(&vals[base + j], x);
         return added;
     }
     ovf = 1;

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
                                                 const int32_t *__restrict__ cA,
                                                 const int32_t *__restrict__ rB,
                                                 const int32_t *__restrict__ cB,
-                                                int32_t *__restrict__ nnz_row, WsHdr *wh, uint32_t hmul) {
+                                                int32_t *__restrict__ nnz_row, WsHdr *wh, HashCfg hc) {
     __shared__ __align__(16) int tab[T];
     __shared__ SegLds<G, false, double> sg;
     const int tid = threadIdx.x;
@@ -291,9 +291,15 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
                 const int c = cB[q[u]];                   // q is always a valid index
                 col[u] = ok[u] ? c : 0;
             }
+            if (hc.bq == 1) {
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hmul);
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) cnt += bkt_insert<false, double, 1>(tab, nullptr, T, col[u], 0.0, ovf, hc.mul);
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hc.mul, hc.bq);
+            }
         };
         auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
         if (PERSIST && cur.a1 - cur.a0 <= G) enum_chunk<G, U, false, double>(cur.lo, cur.hi - cur.lo, 0.0, sg, act);
@@ -742,7 +748,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
                                                 const V *__restrict__ vB,
                                                 const int64_t *__restrict__ rpts_C,
                                                 int32_t *__restrict__ cC, V *__restrict__ vC,
-                                                WsHdr *wh, uint32_t hmul, int64_t ncolsB) {
+                                                WsHdr *wh, HashCfg hc, int64_t ncolsB) {
     __shared__ __align__(16) int keys[T];
     __shared__ V vals[T];
     __shared__ __align__(16) NumLds<G, V> lds;
@@ -776,9 +782,15 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
                 col[u] = ok[u] ? c : 0;
                 x[u] = ok[u] ? av[u] * b : V(0);
             }
+            if (hc.bq == 1) {
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf, hmul);
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) bkt_insert<true, V, 1>(keys, vals, T, col[u], x[u], ovf, hc.mul);
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf, hc.mul, hc.bq);
+            }
         };
         auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
         if (PERSIST && cur.a1 - cur.a0 <= G) enum_chunk<G, U, true, V>(cur.lo, cur.hi - cur.lo, cur.a, sg, act);
@@ -1354,28 +1366,28 @@ hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const
 
 template <int G, int T>
 static void sym_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                       const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, int ncu, hipStream_t s) {
+                       const CsrDev &B, int32_t *nnz_row, WsHdr *wh, HashCfg hc, int ncu, hipStream_t s) {
     constexpr int U = u_for(G, T / 2 + 1);
     // wide bins (few blocks per CU) run persistent; narrow ones a block per row
     constexpr bool P = G >= 512;
     static const int occ = P ? blocks_per_cu(k_sym_hash<G, T, U, P>, G) : 0;
     const unsigned grid = P ? (unsigned)std::min<int64_t>(nrows, (int64_t)ncu * occ) : nrows;
-    k_sym_hash<G, T, U, P><<<grid, G, 0, s>>>(perm, off, nrows, A.rpts, A.cols, B.rpts, B.cols, nnz_row, wh, hmul);
+    k_sym_hash<G, T, U, P><<<grid, G, 0, s>>>(perm, off, nrows, A.rpts, A.cols, B.rpts, B.cols, nnz_row, wh, hc);
 }
 
 hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, int ncu, hipStream_t s) {
+                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, HashCfg hc, int ncu, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     switch (bin) {
-        case 1: sym_hash_l<SYM_G[1], SYM_T[1]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
-        case 2: sym_hash_l<SYM_G[2], SYM_T[2]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
-        case 3: sym_hash_l<SYM_G[3], SYM_T[3]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
-        case 4: sym_hash_l<SYM_G[4], SYM_T[4]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
-        case 5: sym_hash_l<SYM_G[5], SYM_T[5]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
-        case 6: sym_hash_l<SYM_G[6], SYM_T[6]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
-        case 7: sym_hash_l<SYM_G[7], SYM_T[7]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
-        case 8: sym_hash_l<SYM_G[8], SYM_T[8]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
-        case 9: sym_hash_l<SYM_G[9], SYM_T[9]>(nrows, perm, off, A, B, nnz_row, wh, hmul, ncu, s); break;
+        case 1: sym_hash_l<SYM_G[1], SYM_T[1]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 2: sym_hash_l<SYM_G[2], SYM_T[2]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 3: sym_hash_l<SYM_G[3], SYM_T[3]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 4: sym_hash_l<SYM_G[4], SYM_T[4]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 5: sym_hash_l<SYM_G[5], SYM_T[5]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 6: sym_hash_l<SYM_G[6], SYM_T[6]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 7: sym_hash_l<SYM_G[7], SYM_T[7]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 8: sym_hash_l<SYM_G[8], SYM_T[8]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 9: sym_hash_l<SYM_G[9], SYM_T[9]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1470,7 +1482,7 @@ hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &o
 
 template <int G, int T, bool SORTED, typename V>
 static void num_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                       const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, uint32_t hmul, int ncu,
+                       const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, HashCfg hc, int ncu,
                        hipStream_t s) {
     constexpr int U = u_for(G, T / 2 + 1) < 4 ? u_for(G, T / 2 + 1) : 4;
     // wide bins (few blocks per CU) run persistent; narrow ones a block per row
@@ -1478,24 +1490,24 @@ static void num_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const C
     static const int occ = P ? blocks_per_cu(k_num_hash<G, T, U, SORTED, V, P>, G) : 0;
     const unsigned grid = P ? (unsigned)std::min<int64_t>(nrows, (int64_t)ncu * occ) : nrows;
     k_num_hash<G, T, U, SORTED, V, P><<<grid, G, 0, s>>>(perm, off, nrows, A.rpts, A.cols, (const V *)A.vals, B.rpts,
-                                                    B.cols, (const V *)B.vals, rpts_C, cC, (V *)vC, wh, hmul,
+                                                    B.cols, (const V *)B.vals, rpts_C, cC, (V *)vC, wh, hc,
                                                     B.ncols);
 }
 
 template <bool SORTED, typename V>
 static hipError_t num_bin_t(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
                             const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh,
-                            uint32_t hmul, int ncu, hipStream_t s) {
+                            HashCfg hc, int ncu, hipStream_t s) {
     switch (bin) {
-        case 1: num_hash_l<NUM_G[1], NUM_T[1], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
-        case 2: num_hash_l<NUM_G[2], NUM_T[2], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
-        case 3: num_hash_l<NUM_G[3], NUM_T[3], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
-        case 4: num_hash_l<NUM_G[4], NUM_T[4], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
-        case 5: num_hash_l<NUM_G[5], NUM_T[5], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
-        case 6: num_hash_l<NUM_G[6], NUM_T[6], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
-        case 7: num_hash_l<NUM_G[7], NUM_T[7], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
-        case 8: num_hash_l<NUM_G[8], NUM_T[8], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
-        case 9: num_hash_l<NUM_G[9], NUM_T[9], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s); break;
+        case 1: num_hash_l<NUM_G[1], NUM_T[1], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
+        case 2: num_hash_l<NUM_G[2], NUM_T[2], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
+        case 3: num_hash_l<NUM_G[3], NUM_T[3], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
+        case 4: num_hash_l<NUM_G[4], NUM_T[4], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
+        case 5: num_hash_l<NUM_G[5], NUM_T[5], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
+        case 6: num_hash_l<NUM_G[6], NUM_T[6], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
+        case 7: num_hash_l<NUM_G[7], NUM_T[7], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
+        case 8: num_hash_l<NUM_G[8], NUM_T[8], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
+        case 9: num_hash_l<NUM_G[9], NUM_T[9], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1503,13 +1515,13 @@ static hipError_t num_bin_t(int bin, unsigned nrows, const int32_t *perm, int64_
 
 hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
                           const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
-                          WsHdr *wh, uint32_t hmul, int ncu, hipStream_t s) {
+                          WsHdr *wh, HashCfg hc, int ncu, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     if (dtype == 0)
-        return sorted ? num_bin_t<true, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s)
-                      : num_bin_t<false, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s);
-    return sorted ? num_bin_t<true, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu, s)
-                  : num_bin_t<false, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hmul, ncu,
+        return sorted ? num_bin_t<true, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s)
+                      : num_bin_t<false, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s);
+    return sorted ? num_bin_t<true, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s)
+                  : num_bin_t<false, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu,
                                                          s);
 }
 

@@ -28,7 +28,7 @@ hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const
                               int32_t *perm, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh, const BinLimits &L,
                               hipStream_t s);
 hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, uint32_t hmul, int ncu, hipStream_t s);
+                          const CsrDev &B, int32_t *nnz_row, WsHdr *wh, HashCfg hc, int ncu, hipStream_t s);
 hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
                                int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, int ncu,
                                hipStream_t s);
@@ -47,7 +47,7 @@ hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &o
                               const BinLimits &L, hipStream_t s);
 hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
                           const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
-                          WsHdr *wh, uint32_t hmul, int ncu, hipStream_t s);
+                          WsHdr *wh, HashCfg hc, int ncu, hipStream_t s);
 hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
                              const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
                              const void *bv, int32_t *cC, void *vC, const uint32_t *bmap, WsHdr *wh, int ncu,

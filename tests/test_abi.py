@@ -89,6 +89,9 @@ def test_config_rules(lib):
     full = dict(d, sym_max=sym_t[:8] + [8448], num_max=num_t[:8] + [8448])
     assert b.config_ok(full)                                      # tables filled to the brim
     assert b.config_ok(dict(d, hash_mul=0))                       # degenerate hash is allowed
+    assert d["bucket_slots"] == 4
+    assert all(b.config_ok(dict(d, bucket_slots=w)) for w in (4, 8, 16))   # HashVector-style chunks
+    assert not any(b.config_ok(dict(d, bucket_slots=w)) for w in (0, 2, 12, 32))
     assert not b.config_ok(dict(d, sym_max=[65] + d["sym_max"][1:]))          # above the 64-key table
     assert not b.config_ok(dict(d, num_max=d["num_max"][:8] + [8000]))        # must end at 8448
     assert not b.config_ok(dict(d, sym_max=[32, 16] + d["sym_max"][2:]))      # decreasing

@@ -58,6 +58,24 @@ def test_degenerate_hash_is_exact(sp, name, make, srt):
     assert_matches(_run(sp, A, B, srt, cfg), oracle.spgemm(A, B, sorted_output=srt), srt)
 
 
+@pytest.mark.parametrize("slots", [8, 16])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("srt", [True, False])
+def test_wide_buckets_are_exact(sp, slots, name, make, srt):
+    # the HashVector-style chunks (Section 4.2.2): 8- and 16-slot buckets at the
+    # default hash, at full tables and under the worst hash (every key to the
+    # first bucket, so probes run through whole chunks and on to the next)
+    _note(f"case wide buckets {slots} {name} sorted={srt}")
+    from paper_1804_01698_amd import autotune as at
+    A, B = make()
+    B = A if B is None else B
+    ref = oracle.spgemm(A, B, sorted_output=srt)
+    for cfg in (dict(sp.default_config(), bucket_slots=slots),
+                dict(at.make_config(1.0, 1.0, at.HASH_MULS[1]), bucket_slots=slots),
+                dict(sp.default_config(), hash_mul=0, bucket_slots=slots)):
+        assert_matches(_run(sp, A, B, srt, cfg), ref, srt)
+
+
 @pytest.mark.parametrize("load", [0.25, 1.0])
 @pytest.mark.parametrize("srt", [True, False])
 def test_table_loads_are_exact(sp, load, srt):
