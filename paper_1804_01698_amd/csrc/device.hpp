@@ -18,11 +18,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ uint64_t lanemask_le() {
-    const int l = lane_id();
-    return l == 63 ? ~0ull : ((2ull << l) - 1ull);
-}
-
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T x) {
 #pragma unroll
@@ -116,22 +111,6 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
 }
 __device__ __forceinline__ void lds_add(unsigned long long *p, unsigned long long v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Insert-or-accumulate (numeric phase).
-template <typename V>
-__device__ __forceinline__ void num_insert(int *keys, V *vals, uint32_t T, int key, V x, int &ovf) {
-    uint32_t s = hash_slot(key, T);
-    for (uint32_t n = 0; n < T; ++n) {
-        const int cur = lds_load(&keys[s]);
-        if (cur == key) { lds_add(&vals[s], x); return; }
-        if (cur == -1) {
-            const int old = atomicCAS(&keys[s], -1, key);
-            if (old == -1 || old == key) { lds_add(&vals[s], x); return; }
-        }
-        s = (s + 1 == T) ? 0u : s + 1;
-    }
-    ovf = 1;
 }
 
 // ---- bucketed tables (vector probing) ----------------------------------------
