@@ -4,18 +4,22 @@
 //   k_row_flop       row flop (Fig. 4 part 1) + per-bin row counts
 //   k_sym_scatter    rows grouped by flop (GPU counterpart of Fig. 4 part 2)
 //   k_sym_hash<G,T>  symbolic phase: keys-only LDS hash table per row
-//   k_sym_bitmap<W>  symbolic phase for rows above the LDS table range: one
-//                    bit per output column in LDS, plus per-chunk counts
+//   k_sym_bitmap<W>  symbolic phase for rows above the LDS table range
+//                    (persistent): one bit per output column in LDS, plus
+//                    per-chunk counts and, for heavy rows, the bits
 //   k_scan_*         exclusive scan of row counts into int64 row pointers
 //   k_num_hist       rows grouped by exact nnz(c_i) for the numeric phase
-//   k_windows        column windows of the rows too large for one LDS table
+//   k_win_*          column windows of the rows too large for one LDS table
 //   k_bucket_*       B rows reordered by 4096-column chunk, with a chunk index
 //   k_gather_vals    B values in that order (numeric phase)
 //   k_num_hash       numeric phase: LDS hash table of keys + values per row,
-//                    compacted (and sorted if asked) into C
-//   k_num_window     numeric phase of a group of column windows of a heavy row:
-//                    occupancy bits, ranks, values added at their rank
+//                    compacted, or ranked in column passes when sorted
+//   k_num_window     numeric phase of the column windows of heavy rows
+//                    (persistent): occupancy bits, ranks, values and columns
+//                    written at their rank
 //   k_masked_sum     sum of C over the positions of a mask (triangle count)
+//   k_masked_product the same sum without forming C
+//   k_stream_copy, k_stanza_read   copy and stanza-read bandwidth probes
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
