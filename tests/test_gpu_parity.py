@@ -318,12 +318,14 @@ def test_sampled_rows_api(sp):
     assert_rows_match(C, ref, rows, False)
 
 
-def test_sorted_wide_bins_rank_passes(sp):
+@pytest.mark.parametrize("ncols", [300000, 2000000])
+def test_sorted_wide_bins_rank_passes(sp, ncols):
     # rows of the 512- and 1024-thread bins with their columns spread over
-    # 300,000 columns: sorted output ranks them in several column passes
-    _note("case sorted_wide_bins_rank_passes")
+    # 300,000 columns (sorted output ranks them in several column passes) or
+    # over 2,000,000 (more passes than allowed: bitonic sorting)
+    _note(f"case sorted_wide_bins_rank_passes ncols={ncols}")
     rng = np.random.default_rng(21)
-    n, ncols = 4000, 300000
+    n = 4000
     degs = np.repeat([300, 800, 1500, 2000], 8)
     rows = [np.sort(rng.choice(n, size=d, replace=False)) for d in degs]
     rp = np.zeros(len(degs) + 1, dtype=np.int64)
