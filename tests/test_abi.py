@@ -63,6 +63,14 @@ def test_host_side_argument_errors(lib):
     assert st == -1 and not h.value               # invalid config, rejected before any device work
     assert lib.spgemm_symbolic(None, None, None, None) == -1
     assert lib.spgemm_stream_copy(None, None, 15, None) == -1
+    one = ctypes.c_void_p(8)                      # never dereferenced: every call below is rejected first
+    assert lib.spgemm_stanza_read(None, 64, one, 1, 0, one, one, None) == -1        # no array
+    assert lib.spgemm_stanza_read(one, 12, one, 1, 0, one, one, None) == -1         # not whole words
+    assert lib.spgemm_stanza_read(one, 64, one, 1, 25, one, one, None) == -1        # stanza too long
+    assert lib.spgemm_stanza_read(one, 64, one, -1, 0, one, one, None) == -1        # negative count
+    assert lib.spgemm_stanza_read(one, 64, None, 1, 0, one, one, None) == -1        # no starts
+    assert lib.spgemm_stanza_read(one, 64, one, 1, 0, None, one, None) == -1        # no sum
+    assert lib.spgemm_stanza_read(one, 64, one, 1 << 40, 0, one, one, None) == -5   # count overflows
 
 
 def test_plan_scratch_bytes(lib):
