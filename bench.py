@@ -179,35 +179,41 @@ def main():
         del C
         p.close()
 
-    timing = not args.no_timing
-    plans = []
+    # the timed steps: plan through numeric, no per-kernel events; each plan is
+    # released as its step ends (its workspace is reused by the next step)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        p, C, extra = step(timing)
-        plans.append(p)
+        p, C, extra = step(False)
         del C
+        last = p
+        if i + 1 < args.steps:
+            p.close()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / max(args.steps, 1)
 
-    st = plans[-1].stats(0)
+    st = last.stats(0)
+    last.close()
     if st["status"] != 0:
         raise SystemExit(f"device check failed: {st}")
     flop = st["flop"]
     nnz_c = st["nnz_C"]
     gflops = 2.0 * flop / (ms * 1e-3) / 1e9
 
-    # per-kernel times (HIP events on the library's stream, timed region)
+    # per-kernel times: the same steps again with HIP events around every
+    # launch on the library's stream (the events are read after each step)
     agg = {}
-    for p in plans:
-        if timing:
+    if not args.no_timing:
+        for i in range(args.steps):
+            p, C, extra = step(True)
+            del C
             for k in p.kernel_times():
                 a = agg.setdefault(k["name"], dict(ms=0.0, launches=0, alg_bytes=0.0))
                 a["ms"] += k["ms"]
                 a["launches"] += k["launches"]
                 a["alg_bytes"] += k["alg_bytes"]
-        p.close()
+            p.close()
     kernels = sorted(([n, v["ms"] / args.steps, v["launches"] // max(args.steps, 1),
                        v["alg_bytes"] / max(v["launches"], 1)] for n, v in agg.items()),
                      key=lambda r: -r[1])
