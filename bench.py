@@ -227,7 +227,7 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "avg_launch_ms": round(avg_launch_ms, 4), "alg_bytes_per_launch": bytes_per_launch}
     nnz_a, nnz_b, m = inp["A"].nnz, inp["B"].nnz, inp["A"].nrows
-    path_bytes = 16.0 * flop + 12.0 * nnz_c + 44.0 * nnz_a + 40.0 * m
+    path_bytes = path_alg_bytes(flop, nnz_c, nnz_a, m)
     out = {
         "metric": METRIC,
         "value": round(gflops, 2),
@@ -250,6 +250,10 @@ def main():
                           "frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "copy_probe_GBs": round(copy_gbs, 1),
         "kernels_ms_per_step": {k[0]: round(k[1], 4) for k in kernels},
+        "kernels": [{"kernel": k[0], "ms_per_step": round(k[1], 4), "launches": k[2],
+                     "alg_bytes_per_launch": k[3],
+                     "frac": round(k[3] / (k[1] / max(k[2], 1) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if k[1] > 0 else None}
+                    for k in kernels],
     }
     if dM is not None:
         out["triangles"] = int(extra) // 2
@@ -257,6 +261,14 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inp, args.cpu_seconds, srt, args.seed)
     print(json.dumps(out), flush=True)
+
+
+def path_alg_bytes(flop, nnz_c, nnz_a, m):
+    """Algorithmic bytes of one whole product (int32 indices, 8-byte values):
+    16 per multiplication (4 for the symbolic key, 12 for the numeric key and
+    value), 12 per output entry, 36 per entry of A (its column twice, its value,
+    the B row-pointer pair twice) and 40 per row (pointers, flop, counts, scan)."""
+    return 16.0 * flop + 12.0 * nnz_c + 36.0 * nnz_a + 40.0 * m
 
 
 KERNEL_SOURCES = ("paper_1804_01698_amd/csrc/kernels.hip", "paper_1804_01698_amd/csrc/device.hpp",
@@ -294,7 +306,11 @@ def cpu_baseline(inp, seconds, srt, seed):
     block measures the rate; the sample is then sized to about ``seconds``."""
     import oracle
     A, B = inp["A"], inp["B"]
-    f = oracle.row_flop(A, B).astype(np.int64)
+    # step 1 of the oracle (operand validation) once; the row blocks skip it
+    oracle.validate(A)
+    if B is not A:
+        oracle.validate(B)
+    f = oracle.row_flop(A, B, validate_inputs=False).astype(np.int64)
     order = np.random.default_rng(seed + 99).permutation(A.nrows)
     csum = np.cumsum(f[order])
     threads = oracle.max_threads()
@@ -314,7 +330,7 @@ def cpu_baseline(inp, seconds, srt, seed):
                 j += 1
             rows = np.sort(rows_all[i:j])
             t0 = time.perf_counter()
-            C = oracle.spgemm(A, B, sorted_output=srt, rows=rows)
+            C = oracle.spgemm(A, B, sorted_output=srt, rows=rows, validate_inputs=False)
             t += time.perf_counter() - t0
             del C
             done += acc
@@ -332,7 +348,7 @@ def cpu_baseline(inp, seconds, srt, seed):
         total = int(csum[-1])
         while dt < seconds:
             t0 = time.perf_counter()
-            C = oracle.spgemm(A, B, sorted_output=srt)
+            C = oracle.spgemm(A, B, sorted_output=srt, validate_inputs=False)
             dt += time.perf_counter() - t0
             del C
             flop += total
@@ -358,9 +374,15 @@ def _generate_serve(args, small_only: bool = False):
     reqs = [] if small_only else serving_stream(args.requests, args.seed)
     small = serving_stream(args.small_requests, args.seed + 1000, max_flop=2 ** 20)
     workers = max(1, min(16, os.cpu_count() or 1))
-    with mp.get_context("spawn").Pool(workers) as pool:
+    # close() + join() rather than the with-block's terminate(): the workers
+    # exit on their own instead of being sent SIGTERM
+    pool = mp.get_context("spawn").Pool(workers)
+    try:
         main_ops = pool.map(_gen_request, reqs, chunksize=4)
         small_ops = pool.map(_gen_request, small, chunksize=4)
+    finally:
+        pool.close()
+        pool.join()
     log(f"serve: {len(reqs)} + {len(small)} requests generated in {time.perf_counter() - t:.1f}s "
         f"on {workers} processes")
     return main_ops, small_ops
@@ -437,7 +459,7 @@ def bench_sweep(args, sp, dev):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
         flop, nnzc = int(st["flop"]), int(st["nnz_C"])
-        alg = 16.0 * flop + 12.0 * nnzc + 36.0 * A.nnz + 40.0 * A.nrows
+        alg = path_alg_bytes(flop, nnzc, A.nnz, A.nrows)
         rows.append(dict(point=label, **params, nnz_A=int(A.nnz), nnz_B=int(B.nnz), flop=flop, nnz_C=nnzc,
                          ms=round(ms, 4), gflops=round(2.0 * flop / (ms * 1e-3) / 1e9, 2),
                          roofline_frac=round(alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)))

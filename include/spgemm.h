@@ -313,6 +313,15 @@ int spgemm_batch_prepare(int nprod, const spgemm_csr *A, const spgemm_csr *B, co
 int spgemm_batch_analyse(int nprod, const spgemm_csr *A, void *scratch, int64_t *flop, int64_t *bound,
                          int64_t *max_key, hipStream_t stream);
 
+/* Rows of an analysed batch per bin (Fig. 4's row flop grouped as in the
+ * single-product path): rows[0] = empty rows, rows[b] for b = 1..9 = rows whose
+ * key bound min(row flop, ncols) falls in the bin of the b-th LDS table size
+ * (64 ... 16384 slots, see spgemm_config), rows[10] = rows above 8448 (outside
+ * the batched range).  rows is a host array of 11.  Synchronises stream.
+ * Errors: SPGEMM_ERR_INVALID_ARG, SPGEMM_ERR_HIP. */
+enum { SPGEMM_BATCH_BINS = 11 };
+int spgemm_batch_bin_rows(int nprod, const spgemm_csr *A, void *scratch, int64_t *rows, hipStream_t stream);
+
 /* Arena bytes for a batch with the given per-product bounds (host array):
  * 24 bytes per bounded entry plus 8 per row pointer, 256-byte aligned parts. */
 size_t spgemm_batch_arena_bytes(int nprod, const spgemm_csr *A, const int64_t *bound);

@@ -54,6 +54,8 @@ def _load():
     lib.oracle_masked_sum_i64.restype = i64
     lib.oracle_masked_sum_i64.argtypes = [i64, i64, p, p, p, p, p, ctypes.c_int]
     lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_validate_csr.restype = ctypes.c_int
+    lib.oracle_validate_csr.argtypes = [i64, i64, i64, p, p, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -75,13 +77,52 @@ def _rows_arg(rows, nrows):
     return r, r.size
 
 
+_CSR_RULES = {
+    1: "rpts[0] != 0",
+    2: "row pointers decrease",
+    3: "rpts[nrows] != nnz",
+    4: "column id outside [0, ncols)",
+    5: "column repeated within a row",
+    6: "scratch memory unavailable",
+}
+
+
+def validate(a: CSR, allow_duplicates: bool = False) -> None:
+    """Structure check of a CSR operand (CSR as defined in Section 2): row
+    pointers start at 0, never decrease and end at nnz, column ids lie in
+    [0, ncols) and, unless ``allow_duplicates``, no row repeats a column.
+    Raises ValueError naming the first rule that fails."""
+    lib = _load()
+    rp, cols = _prep(a)
+    if rp.size != a.nrows + 1:
+        raise ValueError("malformed CSR: rpts must have nrows + 1 entries")
+    if a.vals is not None and np.asarray(a.vals).size != cols.size:
+        raise ValueError("malformed CSR: vals and cols differ in length")
+    # nnz is the length of the column array; rule 3 checks that rpts ends there
+    st = lib.oracle_validate_csr(a.nrows, a.ncols, cols.size, _ptr(rp), _ptr(cols), 0 if allow_duplicates else 1)
+    if st:
+        raise ValueError(f"malformed CSR: {_CSR_RULES.get(st, st)}")
+
+
+def _check_operands(A: CSR, B: CSR, validate_inputs: bool, allow_duplicates: bool) -> None:
+    if A.ncols != B.nrows:
+        raise ValueError("A.ncols != B.nrows")
+    if validate_inputs:
+        validate(A, allow_duplicates)
+        if B is not A:
+            validate(B, allow_duplicates)
+
+
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
 
 
-def row_flop(A: CSR, B: CSR, rows=None, nthreads: int = 0) -> np.ndarray:
+def row_flop(A: CSR, B: CSR, rows=None, nthreads: int = 0, validate_inputs: bool = True,
+             allow_duplicates: bool = True) -> np.ndarray:
     """flop of each (selected) row of C = A*B: the sum over stored a_ik of nnz(b_k*)
-    (Fig. 4, part 1).  Counts multiplications (Section 2, flop definition)."""
+    (Fig. 4, part 1).  Counts multiplications (Section 2, flop definition); a
+    repeated column counts once per occurrence."""
+    _check_operands(A, B, validate_inputs, allow_duplicates)
     lib = _load()
     rpa, ca = _prep(A)
     rpb, _ = _prep(B)
@@ -101,11 +142,13 @@ def rows_to_threads(flop: np.ndarray, tnum: int) -> np.ndarray:
     return off
 
 
-def symbolic(A: CSR, B: CSR, rows=None, nthreads: int = 0) -> np.ndarray:
+def symbolic(A: CSR, B: CSR, rows=None, nthreads: int = 0, validate_inputs: bool = True,
+             allow_duplicates: bool = False) -> np.ndarray:
     """Symbolic phase (Section 2 two-phase method; Fig. 5): int64 row pointers of
-    C (or of the selected rows of C) from the number of distinct columns per row."""
-    if A.ncols != B.nrows:
-        raise ValueError("A.ncols != B.nrows")
+    C (or of the selected rows of C) from the number of distinct columns per row.
+    Operands are validated first (``validate``) unless ``validate_inputs`` is
+    False (for callers that validated them once already)."""
+    _check_operands(A, B, validate_inputs, allow_duplicates)
     lib = _load()
     rpa, ca = _prep(A)
     rpb, cb = _prep(B)
@@ -128,13 +171,16 @@ def _dtype_code(A: CSR, B: CSR):
     raise TypeError("values must both be float64 or both int64")
 
 
-def spgemm(A: CSR, B: CSR, sorted_output: bool = True, rows=None, nthreads: int = 0) -> CSR:
+def spgemm(A: CSR, B: CSR, sorted_output: bool = True, rows=None, nthreads: int = 0,
+           validate_inputs: bool = True, allow_duplicates: bool = False) -> CSR:
     """C = A*B by Gustavson's row-wise algorithm (Fig. 1) with a sparse accumulator
     (Section 2), two-phase (symbolic then numeric, Fig. 5).  ``rows`` selects a
     subset of rows of C (returned in the given order); rows of C are independent
-    (Section 2), so this equals the same rows of the full product."""
+    (Section 2), so this equals the same rows of the full product.  Operands are
+    validated first (see ``validate``; a repeated column in a row is rejected
+    unless ``allow_duplicates``, and then its products simply add up)."""
     code, dt = _dtype_code(A, B)
-    rp = symbolic(A, B, rows, nthreads)
+    rp = symbolic(A, B, rows, nthreads, validate_inputs, allow_duplicates)
     lib = _load()
     rpa, ca = _prep(A)
     rpb, cb = _prep(B)
@@ -157,6 +203,10 @@ def masked_sum(C: CSR, M: CSR, nthreads: int = 0) -> int:
     C = L*U and M = A this is twice the triangle count (Section 5.6)."""
     if C.vals is None or C.vals.dtype != np.int64:
         raise TypeError("masked_sum needs int64 values")
+    if C.nrows != M.nrows or C.ncols != M.ncols:
+        raise ValueError("C and M differ in shape")
+    validate(C, allow_duplicates=True)     # a product of this oracle: no repeats by construction
+    validate(M)
     lib = _load()
     rpc, cc = _prep(C)
     rpm, cm = _prep(M)
@@ -182,15 +232,3 @@ def lowest_p2(x: int) -> int:
     while p <= x:
         p <<= 1
     return p
-
-
-def hash_table_sizes(A: CSR, B: CSR, tnum: int) -> np.ndarray:
-    """Per-thread hash table size of Fig. 5: lowest_p2(min(N_col, max row flop
-    among the thread's rows)), with rows split by ``rows_to_threads``."""
-    f = row_flop(A, B)
-    off = rows_to_threads(f, tnum)
-    out = np.empty(tnum, dtype=np.int64)
-    for t in range(tnum):
-        mx = int(f[off[t]:off[t + 1]].max()) if off[t + 1] > off[t] else 0
-        out[t] = lowest_p2(min(B.ncols, mx))
-    return out

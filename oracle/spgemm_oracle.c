@@ -39,6 +39,38 @@
 #define OR_F64 0
 #define OR_I64 1
 
+/* -------------------------------------------------------------- validate */
+
+/* Structure check of a CSR operand before any product (the CSR layout of
+ * Section 2: row i holds positions rpts[i] .. rpts[i+1]-1 of cols/vals).
+ * Returns 0 if well formed, else the first failed rule:
+ *   1  rpts[0] != 0          2  rpts decreases somewhere
+ *   3  rpts[nrows] != nnz    4  a column id outside [0, ncols)
+ *   5  a column repeated within a row (checked only if check_dup)
+ *   6  scratch memory unavailable for the repeat check */
+int oracle_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t *rpts,
+                        const int32_t *cols, int check_dup)
+{
+    if (rpts[0] != 0) return 1;
+    for (int64_t i = 0; i < nrows; ++i)
+        if (rpts[i + 1] < rpts[i]) return 2;
+    if (rpts[nrows] != nnz) return 3;
+    for (int64_t p = 0; p < nnz; ++p)
+        if (cols[p] < 0 || (int64_t)cols[p] >= ncols) return 4;
+    if (!check_dup) return 0;
+    int64_t *seen = (int64_t *)malloc((size_t)(ncols > 0 ? ncols : 1) * sizeof(int64_t));
+    if (!seen) return 6;
+    for (int64_t j = 0; j < ncols; ++j) seen[j] = -1;
+    int bad = 0;
+    for (int64_t i = 0; i < nrows && !bad; ++i)
+        for (int64_t p = rpts[i]; p < rpts[i + 1]; ++p) {
+            if (seen[cols[p]] == i) { bad = 5; break; }
+            seen[cols[p]] = i;
+        }
+    free(seen);
+    return bad;
+}
+
 /* ------------------------------------------------------------------ flop */
 
 /* Per-row flop (Fig. 4 part 1) for the selected rows; returns the total. */

@@ -94,6 +94,8 @@ def _load():
                                          ctypes.POINTER(ctypes.c_uint), P, P]
     lib.spgemm_batch_analyse.restype = ctypes.c_int
     lib.spgemm_batch_analyse.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr), P, i64p, i64p, i64p, P]
+    lib.spgemm_batch_bin_rows.restype = ctypes.c_int
+    lib.spgemm_batch_bin_rows.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr), P, i64p, P]
     lib.spgemm_batch_arena_bytes.restype = ctypes.c_size_t
     lib.spgemm_batch_arena_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(_Csr), i64p]
     lib.spgemm_batch_run.restype = ctypes.c_int
@@ -113,6 +115,14 @@ def _check(st: int, where: str):
 def _stream_handle(stream) -> ctypes.c_void_p:
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _on_stream(stream):
+    """The torch stream the library's work goes to (``stream`` or the current
+    one).  Buffers the library uses are allocated on it, so that torch's
+    caching allocator never hands them to other work while the library's
+    kernels still run."""
+    return stream if stream is not None else torch.cuda.current_stream()
 
 
 @dataclass
@@ -210,7 +220,8 @@ class Plan:
         self._ca = (_Csr * self.n)(*[a._c() for a in self.As])
         self._cb = (_Csr * self.n)(*[b._c() for b in self.Bs])
         nbytes = _lib.spgemm_plan_scratch_bytes(self.n, self._ca)
-        self.plan_scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+        with torch.cuda.stream(_on_stream(stream)):
+            self.plan_scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
         ws = ctypes.c_size_t(0)
         flags = ((SORTED if self.sorted else 0) | (VALIDATE if validate else 0) | (TIMING if timing else 0)
                  | (LOW_MEMORY if low_memory else 0))
@@ -229,7 +240,8 @@ class Plan:
 
     def allocate_workspace(self):
         if self.workspace is None:
-            self.workspace = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=self.device)
+            with torch.cuda.stream(_on_stream(self.stream)):
+                self.workspace = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=self.device)
 
     def output_bytes(self) -> int:
         """Device bytes of C (after symbolic): int32 columns and 8-byte values."""
@@ -237,7 +249,8 @@ class Plan:
 
     def symbolic(self) -> List[int]:
         self.allocate_workspace()
-        self.rpts_C = [torch.empty(a.nrows + 1, dtype=torch.int64, device=self.device) for a in self.As]
+        with torch.cuda.stream(_on_stream(self.stream)):
+            self.rpts_C = [torch.empty(a.nrows + 1, dtype=torch.int64, device=self.device) for a in self.As]
         arr = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in self.rpts_C])
         nnz = (ctypes.c_int64 * self.n)()
         st = _lib.spgemm_symbolic(self._h, ctypes.c_void_p(self.workspace.data_ptr()), arr, nnz)
@@ -247,9 +260,10 @@ class Plan:
 
     def allocate_output(self):
         vt = torch.float64 if self.dtype == F64 else torch.int64
-        self.C = [DeviceCSR(a.nrows, b.ncols, rp, torch.empty(nz, dtype=torch.int32, device=self.device),
-                            torch.empty(nz, dtype=vt, device=self.device))
-                  for a, b, rp, nz in zip(self.As, self.Bs, self.rpts_C, self.nnz_C)]
+        with torch.cuda.stream(_on_stream(self.stream)):
+            self.C = [DeviceCSR(a.nrows, b.ncols, rp, torch.empty(nz, dtype=torch.int32, device=self.device),
+                                torch.empty(nz, dtype=vt, device=self.device))
+                      for a, b, rp, nz in zip(self.As, self.Bs, self.rpts_C, self.nnz_C)]
         return self.C
 
     def numeric(self, As: Optional[Sequence[DeviceCSR]] = None, Bs: Optional[Sequence[DeviceCSR]] = None):
@@ -342,7 +356,8 @@ class Batch:
         nb = _lib.spgemm_batch_scratch_bytes(self.n, self._ca)
         if nb == 0:
             raise SpgemmError(-1, "spgemm_batch_scratch_bytes: invalid batch")
-        self.scratch = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        with torch.cuda.stream(_on_stream(stream)):
+            self.scratch = torch.empty(nb, dtype=torch.uint8, device=self.device)
         flags = (ctypes.c_uint * self.n)(*[SORTED if x else 0 for x in self.sorted])
         _check(_lib.spgemm_batch_prepare(self.n, self._ca, self._cb, flags,
                                          ctypes.c_void_p(self.scratch.data_ptr()), _stream_handle(stream)),
@@ -362,6 +377,14 @@ class Batch:
         if allocate:
             self.allocate()
 
+    def bin_rows(self) -> List[int]:
+        """Rows of the batch per bin: [empty, bins 1..9 (the LDS table sizes),
+        outside the batched range] (spgemm_batch_bin_rows)."""
+        out = (ctypes.c_int64 * 11)()
+        _check(_lib.spgemm_batch_bin_rows(self.n, self._ca, ctypes.c_void_p(self.scratch.data_ptr()), out,
+                                          _stream_handle(self.stream)), "spgemm_batch_bin_rows")
+        return [int(x) for x in out]
+
     @property
     def supported(self) -> List[bool]:
         """Products whose every row lies inside the batched range."""
@@ -369,8 +392,9 @@ class Batch:
 
     def allocate(self):
         if self.arena is None:
-            self.arena = torch.empty(max(self.arena_bytes, 1), dtype=torch.uint8, device=self.device)
-            self.results = torch.zeros(self.n * BATCH_RESULT_BYTES, dtype=torch.uint8, device=self.device)
+            with torch.cuda.stream(_on_stream(self.stream)):
+                self.arena = torch.empty(max(self.arena_bytes, 1), dtype=torch.uint8, device=self.device)
+                self.results = torch.zeros(self.n * BATCH_RESULT_BYTES, dtype=torch.uint8, device=self.device)
 
     def run(self, stream=None):
         if self.arena is None:
@@ -417,14 +441,18 @@ def spgemm(A: DeviceCSR, B: DeviceCSR, sorted_output: bool = True, validate: boo
 
 
 def masked_sum_i64(C: DeviceCSR, M: DeviceCSR, stream=None) -> int:
-    """Sum of C_ij over the positions stored in M (int64, wrap-around), on the device."""
-    out = torch.empty(1, dtype=torch.int64, device=C.cols.device)
+    """Sum of C_ij over the positions stored in M (int64, wrap-around), on the device.
+    The output is allocated on ``stream`` and read back after that stream is done."""
+    s = _on_stream(stream)
+    with torch.cuda.stream(s):
+        out = torch.empty(1, dtype=torch.int64, device=C.cols.device)
     m = _Csr(M.nrows, M.ncols, M.nnz, M.rpts.data_ptr(), M.cols.data_ptr() if M.nnz else None, None)
     st = _lib.spgemm_masked_sum_i64(C.nrows, C.ncols, ctypes.c_void_p(C.rpts.data_ptr()),
                                     ctypes.c_void_p(C.cols.data_ptr() if C.nnz else None),
                                     ctypes.c_void_p(C.vals.data_ptr() if C.nnz else None),
-                                    ctypes.byref(m), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+                                    ctypes.byref(m), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s.cuda_stream))
     _check(st, "spgemm_masked_sum_i64")
+    s.synchronize()
     return int(out.item())
 
 
@@ -433,10 +461,14 @@ MASKED_WS_BYTES = 256
 
 def masked_product_sum_i64(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, ones: bool = False, stream=None) -> int:
     """Sum of (A*B)_ij over the positions stored in M, without forming A*B
-    (int64, wrap-around).  ones=True counts products (every value 1)."""
+    (int64, wrap-around).  ones=True counts products (every value 1).  The
+    workspace and output are allocated on ``stream`` and read back after that
+    stream is done."""
     dev = A.rpts.device
-    ws = torch.empty(MASKED_WS_BYTES, dtype=torch.uint8, device=dev)
-    out = torch.empty(1, dtype=torch.int64, device=dev)
+    s = _on_stream(stream)
+    with torch.cuda.stream(s):
+        ws = torch.empty(MASKED_WS_BYTES, dtype=torch.uint8, device=dev)
+        out = torch.empty(1, dtype=torch.int64, device=dev)
     ca, cb = A._c(), B._c()
     if ones:
         ca.vals = None
@@ -444,8 +476,9 @@ def masked_product_sum_i64(A: DeviceCSR, B: DeviceCSR, M: DeviceCSR, ones: bool 
     m = _Csr(M.nrows, M.ncols, M.nnz, M.rpts.data_ptr(), M.cols.data_ptr() if M.nnz else None, None)
     st = _lib.spgemm_masked_product_sum_i64(ctypes.byref(ca), ctypes.byref(cb), ctypes.byref(m),
                                             ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                            _stream_handle(stream))
+                                            ctypes.c_void_p(s.cuda_stream))
     _check(st, "spgemm_masked_product_sum_i64")
+    s.synchronize()
     return int(out.item())
 
 

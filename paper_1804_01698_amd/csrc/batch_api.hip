@@ -172,6 +172,19 @@ int spgemm_batch_analyse(int nprod, const spgemm_csr *A, void *scratch, int64_t 
     return SPGEMM_OK;
 }
 
+int spgemm_batch_bin_rows(int nprod, const spgemm_csr *A, void *scratch, int64_t *rows, hipStream_t stream) {
+    if (nprod <= 0 || !A || !scratch || !rows) return SPGEMM_ERR_INVALID_ARG;
+    const int64_t mtot = total_rows(nprod, A);
+    if (mtot < 0) return SPGEMM_ERR_INVALID_ARG;
+    const ScratchLayout L = scratch_layout(nprod, mtot);
+    unsigned h[BAT_NB];
+    hipError_t e = hipMemcpyAsync(h, (char *)scratch + L.bcnt, sizeof(h), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return SPGEMM_ERR_HIP;
+    for (int b = 0; b < BAT_NB; ++b) rows[b] = (int64_t)h[b];
+    return SPGEMM_OK;
+}
+
 size_t spgemm_batch_arena_bytes(int nprod, const spgemm_csr *A, const int64_t *bound) {
     if (nprod <= 0 || !A || !bound) return 0;
     const int64_t mtot = total_rows(nprod, A);

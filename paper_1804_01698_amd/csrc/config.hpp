@@ -5,9 +5,11 @@
 namespace spg {
 
 // ---- heavy rows: column windows --------------------------------------------
-// Rows whose output does not fit one LDS table are accumulated window by
-// window; a window is a run of whole 4096-column chunks holding at most
-// WIN_CAP output entries, accumulated in a WIN_TABLE-slot LDS hash table.
+// Rows whose output does not fit one LDS table (more than WIN_CAP entries)
+// are accumulated window by window; a window is a run of whole 4096-column
+// chunks whose LDS footprint (below) fits RANK_BUDGET words, which bounds it
+// at about 11.6 K output entries.  WIN_TABLE is the largest numeric hash
+// table (bin 9), sized for WIN_CAP entries at a load of at most 0.75.
 constexpr int CHUNK_SHIFT = 12;
 constexpr int CHUNK_COLS = 1 << CHUNK_SHIFT;
 constexpr int WIN_TABLE = 11264;   // 132 KB of keys+values for 8-byte values

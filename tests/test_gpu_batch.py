@@ -46,8 +46,18 @@ def test_batch_matches_oracle(sp):
     flags.append(True)
     pairs.append((random_sparse(30, 20, 0.0, 1), random_sparse(20, 9, 0.3, 2)))   # all rows empty
     flags.append(False)
+    # fixed-degree products whose rows fall in the 4096-, 8192- and 16384-slot
+    # tables (key bounds 1600, 2500 and 4900 with 20,000 columns)
+    for d, seed in ((40, 61), (50, 62), (70, 63)):
+        a = erdos_renyi_fixed_degree(600, d, seed, ncols=20000)
+        b = erdos_renyi_fixed_degree(20000, d, seed + 10)
+        pairs.append((a, b))
+        flags.append(seed % 2 == 0)
     dev = [(sp.DeviceCSR.from_host(a), sp.DeviceCSR.from_host(b)) for a, b in pairs]
     bt = sp.Batch([x for x, _ in dev], [y for _, y in dev], flags)
+    bins = bt.bin_rows()
+    assert all(bins[b] > 0 for b in range(1, 10)), bins    # every LDS table size is used
+    assert bins[10] == 0 and sum(bins) == sum(a.nrows for a, _ in pairs)
     bt.run()
     torch.cuda.synchronize()
     outs = bt.outputs()

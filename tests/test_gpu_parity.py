@@ -337,3 +337,82 @@ def test_sorted_wide_bins_rank_passes(sp, ncols):
     for srt in (True, False):
         C = _run(sp, shuffle_within_rows(A, 5), B, srt)
         assert_matches(C, oracle.spgemm(A, B, sorted_output=srt), srt)
+
+
+def test_masked_sums_on_a_side_stream(sp):
+    """Masked sums launched on a non-default stream: the binding allocates on
+    that stream and reads the result only after it is done."""
+    import torch
+    _note("case masked sums on a side stream")
+    g = symmetric_rmat_graph(12, 16, 5)
+    A, L, U = triangle_inputs(g, degree_order=False)
+    ref = oracle.triangle_count(A, L, U)
+    dA, dL, dU = _dev(sp, A), _dev(sp, L), _dev(sp, U)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        # keep the current stream busy so that a read on it would run early
+        busy = torch.randn(1 << 22, device="cuda")
+        for _ in range(8):
+            busy = busy * 1.0001
+        assert sp.triangle_count(dA, dL, dU, stream=side) == ref
+        assert sp.triangle_count(dA, dL, dU, stream=side, fused=False) == ref
+    torch.cuda.synchronize()
+
+
+def test_numeric_before_symbolic_is_a_state_error(sp):
+    """spgemm_numeric on a plan whose symbolic phase has not run, or with
+    operands other than the planned ones, returns SPGEMM_ERR_STATE (-6)."""
+    import ctypes
+    import torch
+    from paper_1804_01698_amd import binding as b
+    _note("case state errors")
+    A = random_sparse(50, 40, 0.2, 1)
+    B = random_sparse(40, 30, 0.2, 2)
+    dA, dB = _dev(sp, A), _dev(sp, B)
+    p = sp.Plan([dA], [dB])
+    out_c = torch.empty(1, dtype=torch.int32, device="cuda")
+    out_v = torch.empty(1, dtype=torch.float64, device="cuda")
+    cc = (ctypes.c_void_p * 1)(out_c.data_ptr())
+    cv = (ctypes.c_void_p * 1)(out_v.data_ptr())
+    assert b._lib.spgemm_numeric(p._h, p._ca, p._cb, cc, cv) == -6
+    p.symbolic()
+    other = _dev(sp, random_sparse(50, 40, 0.2, 3))
+    ca = (b._Csr * 1)(other._c())
+    C = p.allocate_output()[0]
+    cc = (ctypes.c_void_p * 1)(C.cols.data_ptr())
+    cv = (ctypes.c_void_p * 1)(C.vals.data_ptr())
+    assert b._lib.spgemm_numeric(p._h, ca, p._cb, cc, cv) == -6      # not the planned A
+    assert b._lib.spgemm_numeric(p._h, p._ca, p._cb, cc, cv) == 0
+    torch.cuda.synchronize()
+    assert_matches(C, oracle.spgemm(A, B), True)
+    p.close()
+
+
+def test_repeated_input_columns_add_up(sp):
+    """A row of A or B may repeat a column (the library's documented reading):
+    its products add up, as the oracle computes when repeats are allowed."""
+    _note("case repeated input columns")
+    rng = np.random.default_rng(8)
+    for seed in range(3):
+        A = random_sparse(200, 150, 0.05, 30 + seed)
+        B = random_sparse(150, 300, 0.05, 40 + seed)
+        # repeat about a tenth of the entries of each operand inside their rows
+        def dup(X, s):
+            r = np.random.default_rng(s)
+            rows, cols, vals = [], [], []
+            for i in range(X.nrows):
+                c = X.cols[X.rpts[i]:X.rpts[i + 1]]
+                v = X.vals[X.rpts[i]:X.rpts[i + 1]]
+                pick = r.random(c.size) < 0.1
+                cc = np.concatenate([c, c[pick]])
+                vv = np.concatenate([v, r.random(int(pick.sum()))])
+                o = r.permutation(cc.size)
+                rows.append(cc[o]); vals.append(vv[o])
+            rp = np.zeros(X.nrows + 1, dtype=np.int64)
+            np.cumsum([x.size for x in rows], out=rp[1:])
+            return CSR(X.nrows, X.ncols, rp, np.concatenate(rows).astype(np.int32), np.concatenate(vals))
+        Ad, Bd = dup(A, seed), dup(B, seed + 10)
+        for srt in (True, False):
+            C = _run(sp, Ad, Bd, srt)
+            assert_matches(C, oracle.spgemm(Ad, Bd, sorted_output=srt, allow_duplicates=True), srt)

@@ -96,10 +96,52 @@ def test_i64_wraps_modulo_2_64():
 
 
 def test_duplicate_input_columns_add_up():
+    # A repeated column is rejected by default; read as the sum of its entries
+    # (a_01 = 1 + 2) when allowed, it gives row 0 of [[0, 3, 4]] @ B.
     A = CSR(1, 3, np.array([0, 3]), np.array([1, 1, 2]), np.array([1.0, 2.0, 4.0]))
     B = from_dense(np.array([[0, 0], [1, 0], [0, 1]], dtype=np.float64))
-    C = oracle.spgemm(A, B)
+    with pytest.raises(ValueError, match="repeated"):
+        oracle.spgemm(A, B)
+    C = oracle.spgemm(A, B, allow_duplicates=True)
     assert sorted(zip(C.cols.tolist(), C.vals.tolist())) == [(0, 3.0), (1, 4.0)]
+    ref = np.array([[0, 3.0, 4.0]]) @ to_dense(B)
+    assert np.array_equal(to_dense(C), ref)
+
+
+def _bad(nrows, ncols, rp, cols):
+    return CSR(nrows, ncols, np.array(rp, dtype=np.int64), np.array(cols, dtype=np.int32),
+               np.ones(len(cols)))
+
+
+@pytest.mark.parametrize("bad,rule", [
+    (_bad(2, 3, [1, 1, 2], [0, 1]), "rpts\\[0\\]"),                 # does not start at 0
+    (_bad(2, 3, [0, 2, 1], [0, 1]), "decrease"),                     # row pointers decrease
+    (_bad(2, 3, [0, 1, 1], [0, 1]), "nnz"),                          # end short of nnz
+    (_bad(2, 3, [0, 1, 2], [0, 3]), "outside"),                      # column id == ncols
+    (_bad(2, 3, [0, 1, 2], [-1, 0]), "outside"),                     # negative column id
+    (_bad(1, 3, [0, 2], [2, 2]), "repeated"),                        # repeated column
+])
+def test_validate_rejects_malformed_csr(bad, rule):
+    """Step 1 of the oracle: malformed operands are rejected before any product,
+    whichever side they are on."""
+    good = random_sparse(3, 2, 0.5, 1)
+    with pytest.raises(ValueError, match=rule):
+        oracle.validate(bad)
+    with pytest.raises(ValueError, match=rule):
+        oracle.spgemm(bad, random_sparse(bad.ncols, 4, 0.5, 2))
+    with pytest.raises(ValueError, match=rule):
+        oracle.symbolic(good, bad) if bad.nrows == 2 else oracle.symbolic(random_sparse(5, 1, 0.5, 3), bad)
+
+
+def test_validate_shape_and_lengths():
+    A = random_sparse(4, 5, 0.5, 1)
+    with pytest.raises(ValueError, match="A.ncols"):
+        oracle.spgemm(A, random_sparse(6, 3, 0.5, 2))
+    short = CSR(4, 5, A.rpts[:-1], A.cols, A.vals)
+    with pytest.raises(ValueError, match="nrows"):
+        oracle.validate(short)
+    for g in (A, rmat(8, 8, 3), erdos_renyi_fixed_degree(100, 5, 4)):
+        oracle.validate(g)                                          # well formed: no error
 
 
 # ---------------------------------------------------------------- P2: flop invariant
@@ -326,11 +368,3 @@ def test_rows_to_threads_lower_bound(tnum):
 def test_lowest_p2_is_strict():
     assert [oracle.lowest_p2(x) for x in (0, 1, 2, 3, 4, 7, 8, 1023, 1024)] == \
         [1, 2, 4, 4, 8, 8, 16, 1024, 2048]
-
-
-def test_hash_table_sizes_clamp_to_ncols():
-    A = rmat(9, 16, 17)
-    sizes = oracle.hash_table_sizes(A, A, 4)
-    f = oracle.row_flop(A, A)
-    assert np.all(sizes > np.minimum(A.ncols, f.max()) // 2)
-    assert np.all(sizes <= 2 * A.ncols)
