@@ -78,7 +78,9 @@ enum {
     SPGEMM_ERR_HIP = -7,          /* a HIP runtime call failed                         */
     SPGEMM_ERR_UNSUPPORTED = -8,  /* input outside the supported envelope              */
     SPGEMM_ERR_HOST_ALLOC = -9,   /* host memory for the plan could not be allocated   */
-    SPGEMM_ERR_INTERNAL = -10     /* a device-side consistency check failed            */
+    SPGEMM_ERR_INTERNAL = -10,    /* a device-side consistency check failed            */
+    SPGEMM_ERR_STATIC_LIMIT = -11 /* the plan needs more workspace than the static
+                                     scratch of spgemm_symbolic_static holds          */
 };
 
 /*
@@ -166,6 +168,24 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
  *              until spgemm_free
  */
 int spgemm_symbolic(spgemm_plan_t plan, void *workspace, int64_t *const *rpts_C, int64_t *nnz_C);
+
+/*
+ * spgemm_symbolic without a workspace argument, for callers that cannot
+ * allocate device memory (serving loops and harnesses that forbid hipMalloc):
+ * the workspace is a static device array of SPGEMM_STATIC_WS_BYTES bytes that
+ * the library holds on every GPU it runs on until the process ends.  The
+ * current device must be the device of the plan's stream.  A plan whose
+ * workspace (spgemm_plan's workspace_bytes) exceeds SPGEMM_STATIC_WS_BYTES is
+ * rejected with SPGEMM_ERR_STATIC_LIMIT before any work is enqueued.
+ * Otherwise this is spgemm_symbolic with that array as the workspace: same
+ * outputs, same synchronisation, and the plan's spgemm_numeric reads the array
+ * too.  Every call on a GPU shares that GPU's array, which keeps the last
+ * call's contents: from this call until the same plan's spgemm_numeric has
+ * finished on its stream, another spgemm_symbolic_static on the same GPU
+ * races with it (its results are undefined).  Nothing is allocated.
+ */
+enum { SPGEMM_STATIC_WS_BYTES = 64 << 20 };
+int spgemm_symbolic_static(spgemm_plan_t plan, int64_t *const *rpts_C, int64_t *nnz_C);
 
 /*
  * Numeric phase.  A and B must describe the same matrices (same pointers for

@@ -66,6 +66,8 @@ def _load():
     lib.spgemm_config_check.argtypes = [ctypes.POINTER(_Config)]
     lib.spgemm_symbolic.restype = ctypes.c_int
     lib.spgemm_symbolic.argtypes = [P, P, pp, i64p]
+    lib.spgemm_symbolic_static.restype = ctypes.c_int
+    lib.spgemm_symbolic_static.argtypes = [P, pp, i64p]
     lib.spgemm_numeric.restype = ctypes.c_int
     lib.spgemm_numeric.argtypes = [P, ctypes.POINTER(_Csr), ctypes.POINTER(_Csr), pp, pp]
     lib.spgemm_free.restype = ctypes.c_int
@@ -255,6 +257,18 @@ class Plan:
         nnz = (ctypes.c_int64 * self.n)()
         st = _lib.spgemm_symbolic(self._h, ctypes.c_void_p(self.workspace.data_ptr()), arr, nnz)
         _check(st, "spgemm_symbolic")
+        self.nnz_C = [int(x) for x in nnz]
+        return self.nnz_C
+
+    def symbolic_static(self) -> List[int]:
+        """spgemm_symbolic_static: the symbolic phase in the library's static
+        per-GPU workspace (no workspace tensor; rpts_C is still the caller's)."""
+        with torch.cuda.stream(_on_stream(self.stream)):
+            self.rpts_C = [torch.empty(a.nrows + 1, dtype=torch.int64, device=self.device) for a in self.As]
+        arr = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in self.rpts_C])
+        nnz = (ctypes.c_int64 * self.n)()
+        st = _lib.spgemm_symbolic_static(self._h, arr, nnz)
+        _check(st, "spgemm_symbolic_static")
         self.nnz_C = [int(x) for x in nnz]
         return self.nnz_C
 

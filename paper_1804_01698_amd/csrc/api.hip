@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -142,6 +143,30 @@ size_t plan_scratch_one(int64_t m, int64_t nnz) {
     return PLAN_HDR_BYTES + align_up((size_t)m * 4) + align_up((size_t)nnz * 4);
 }
 
+// Workspace of spgemm_symbolic_static.  Each GPU the library runs on holds
+// its own copy until the process ends; host code reaches it only through
+// the address hipGetSymbolAddress gives for the current device.
+static __device__ __align__(256) unsigned char scratch[SPGEMM_STATIC_WS_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the static workspace on device dev (which is current),
+// resolved on the first call per device.
+int static_workspace(int dev, void **out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return SPGEMM_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) return SPGEMM_ERR_INTERNAL;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPGEMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -169,6 +194,8 @@ const char *spgemm_strerror(int status) {
         case SPGEMM_ERR_UNSUPPORTED: return "input outside the supported envelope";
         case SPGEMM_ERR_HOST_ALLOC: return "host allocation failed";
         case SPGEMM_ERR_INTERNAL: return "device-side consistency check failed";
+        case SPGEMM_ERR_STATIC_LIMIT:
+            return "the plan's workspace exceeds the static scratch of spgemm_symbolic_static (64 MiB)";
         default: return "unknown status";
     }
 }
@@ -423,6 +450,20 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
     if (bad) return SPGEMM_ERR_INTERNAL;
     pl->state = SYMBOLIC_DONE;
     return SPGEMM_OK;
+}
+
+int spgemm_symbolic_static(spgemm_plan_t pl, int64_t *const *rpts_C, int64_t *nnz_C) {
+    if (!pl || !rpts_C || !nnz_C) return SPGEMM_ERR_INVALID_ARG;
+    if (pl->state < PLANNED) return SPGEMM_ERR_STATE;
+    if (pl->ws_total > (size_t)SPGEMM_STATIC_WS_BYTES) return SPGEMM_ERR_STATIC_LIMIT;
+    int cur = 0, sdev = 0;
+    HIPCK(hipGetDevice(&cur), "hipGetDevice");
+    HIPCK(hipStreamGetDevice(pl->stream, &sdev), "hipStreamGetDevice");
+    if (cur != sdev) return SPGEMM_ERR_INVALID_ARG;
+    void *ws = nullptr;
+    const int st = static_workspace(cur, &ws);
+    if (st != SPGEMM_OK) return st;
+    return spgemm_symbolic(pl, ws, rpts_C, nnz_C);
 }
 
 int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, int32_t *const *cols_C,
