@@ -60,20 +60,28 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_inputs(name: str, seed: int, sorted_flag):
+def input_rows_sorted(srt: bool, input_order: str) -> bool:
+    """Whether the input rows come sorted by column: with the output's order
+    (the paper's unsorted runs shuffle the input rows, Section 5.1) unless
+    --input-order fixes it."""
+    return srt if input_order == "auto" else input_order == "sorted"
+
+
+def make_inputs(name: str, seed: int, sorted_flag, input_order: str = "auto"):
     from synth import (bfs_frontier, erdos_renyi_fixed_degree, rmat, shuffle_within_rows,
                        symmetric_rmat_graph, triangle_inputs, with_values)
     w = WORKLOADS[name]
     srt = w["sorted"] if sorted_flag is None else sorted_flag
+    rows_sorted = input_rows_sorted(srt, input_order)
     if name == "rmat20":
-        A = rmat(20, 16, seed, sorted_rows=srt)
-        return dict(A=A, B=A, sorted=srt)
+        A = rmat(20, 16, seed, sorted_rows=rows_sorted)
+        return dict(A=A, B=A, sorted=srt, rows_sorted=rows_sorted)
     if name == "er20":
-        A = erdos_renyi_fixed_degree(1 << 20, 16, seed, sorted_rows=srt)
-        return dict(A=A, B=A, sorted=srt)
+        A = erdos_renyi_fixed_degree(1 << 20, 16, seed, sorted_rows=rows_sorted)
+        return dict(A=A, B=A, sorted=srt, rows_sorted=rows_sorted)
     if name == "rmat16":
-        A = rmat(16, 16, seed, sorted_rows=srt)
-        return dict(A=A, B=A, sorted=srt)
+        A = rmat(16, 16, seed, sorted_rows=rows_sorted)
+        return dict(A=A, B=A, sorted=srt, rows_sorted=rows_sorted)
     if name == "er4096":
         A = erdos_renyi_fixed_degree(4096, 8, seed, sorted_rows=True)
         return dict(A=A, B=A, sorted=srt)
@@ -96,6 +104,9 @@ def main():
     ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
     ap.add_argument("--sorted", dest="sorted_flag", action="store_true", default=None)
     ap.add_argument("--unsorted", dest="sorted_flag", action="store_false")
+    ap.add_argument("--input-order", default="auto", choices=("auto", "sorted", "shuffled"),
+                    help="column order inside the input rows (rmat20, er20, rmat16); auto: sorted "
+                         "for sorted output, shuffled for unsorted output")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -134,7 +145,7 @@ def main():
         return bench_stanza(args, sp, dev)
 
     t_gen = time.perf_counter()
-    inp = make_inputs(args.workload, args.seed, args.sorted_flag)
+    inp = make_inputs(args.workload, args.seed, args.sorted_flag, args.input_order)
     if args.workload == "tri18f":
         return bench_tri_fused(args, sp, dev, inp)
     log(f"inputs {args.workload}: generated in {time.perf_counter() - t_gen:.1f}s; "
@@ -178,23 +189,31 @@ def main():
         log(f"warmup {i}: nnz(C) = {st['nnz_C']}, flop = {st['flop']}, windows = {st['windows']}")
         del C
         p.close()
+        del p
 
-    # the timed steps: plan through numeric, no per-kernel events; each plan is
-    # released as its step ends (its workspace is reused by the next step)
+    # the timed steps: plan through numeric, no per-kernel events.  Every step
+    # drops its plan (and with it the workspace) and C before the next one
+    # starts, so each step's buffers come from the allocator's cache of the
+    # previous step's; the last plan is kept for its counters.
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ms = []
     for i in range(args.steps):
+        ts = time.perf_counter()
         p, C, extra = step(False)
         del C
-        last = p
         if i + 1 < args.steps:
             p.close()
+            del p
+        step_ms.append((time.perf_counter() - ts) * 1e3)     # host time to enqueue/return
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / max(args.steps, 1)
+    log("step host ms: " + ", ".join(f"{x:.1f}" for x in step_ms))
 
-    st = last.stats(0)
-    last.close()
+    st = p.stats(0)
+    p.close()
+    del p
     if st["status"] != 0:
         raise SystemExit(f"device check failed: {st}")
     flop = st["flop"]
@@ -214,6 +233,7 @@ def main():
                 a["launches"] += k["launches"]
                 a["alg_bytes"] += k["alg_bytes"]
             p.close()
+            del p
     kernels = sorted(([n, v["ms"] / args.steps, v["launches"] // max(args.steps, 1),
                        v["alg_bytes"] / max(v["launches"], 1)] for n, v in agg.items()),
                      key=lambda r: -r[1])
@@ -242,7 +262,8 @@ def main():
         "dtype": "i64" if inp["A"].vals.dtype == np.int64 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]['desc']}",
-                   "sorted_output": srt, "nrows": m, "nnz_A": nnz_a, "nnz_B": nnz_b, "flop": flop,
+                   "sorted_output": srt, "input_rows": ("sorted" if inp.get("rows_sorted") else "shuffled")
+                   if "rows_sorted" in inp else None, "nrows": m, "nnz_A": nnz_a, "nnz_B": nnz_b, "flop": flop,
                    "nnz_C": nnz_c, "seed": args.seed},
         "roofline": roofline,
         "path_roofline": {"alg_bytes": path_bytes, "achieved": round(path_bytes / (ms * 1e-3) / 1e9, 1),

@@ -58,6 +58,9 @@ enum {
                                   ids in range); failure gives SPGEMM_ERR_INVALID_CSR */
     SPGEMM_TIMING = 1u << 2,   /* record HIP events around every kernel launch from
                                   the plan on (see spgemm_plan_kernel_times)        */
+    SPGEMM_PROBE_COUNT = 1u << 4, /* count the bucket reads of every hash-table
+                                  insertion per bin (spgemm_stats: the collision
+                                  factor of Eq. 2); a debugging aid, not free   */
     SPGEMM_LOW_MEMORY = 1u << 3 /* do not keep the symbolic bitmaps of rows whose
                                   key bound exceeds 8448 for the numeric phase: a
                                   smaller workspace (by nrows_in_that_bin *
@@ -128,14 +131,23 @@ size_t spgemm_plan_scratch_bytes(int nprod, const spgemm_csr *A);
  * tables' buckets: a key's bucket is scanned 4 slots (one 16-byte LDS load)
  * at a time, front to back, and a full bucket passes the probe to the next;
  * 8 and 16 are the wider chunks of the HashVector variant (Section 4.2.2).
- * The defaults (spgemm_config_default) fill each table at most half and use
- * 4-slot buckets.
+ * heap = 1 selects the Heap accumulator of Section 4.2.3 for the numeric
+ * phase of every row whose output fits an LDS table, that has at most 256
+ * entries of A and at most 1024 products: the row is merged from the sorted
+ * rows of B by a priority queue of nnz(a_i) heads and leaves sorted (Eq. 1
+ * costs it flop * log nnz(a_i)); other rows keep the hash tables.  It needs
+ * SPGEMM_SORTED (else spgemm_plan returns SPGEMM_ERR_INVALID_ARG) and rows of B
+ * in ascending column order (checked on the device by spgemm_plan, which
+ * returns SPGEMM_ERR_UNSUPPORTED otherwise).  heap = 0: hash tables only.
+ * The defaults (spgemm_config_default) fill each table at most half, use
+ * 4-slot buckets and no heap.
  */
 typedef struct {
     uint32_t hash_mul;
     int32_t sym_max[9];
     int32_t num_max[9];
     uint32_t bucket_slots;
+    uint32_t heap;
 } spgemm_config;
 
 /* The default configuration. */
@@ -213,6 +225,16 @@ typedef struct {
     int64_t heavy_rows;      /* rows accumulated in column windows                  */
     int64_t windows;         /* column-window work items of those rows              */
     int64_t probe_overflow;  /* must be 0: hash probes that exceeded the table size */
+    int64_t heap_rows;       /* rows whose numeric phase took the heap merge        */
+    /* Collision factor of Eq. 2 per LDS table bin b = 1..9 (index b-1):
+     * c = probes / flop, the 16-byte bucket reads per insertion.  probes are
+     * counted only in plans made with SPGEMM_PROBE_COUNT (else 0); flop is
+     * the bin's multiplications (symbolic bins by key bound, numeric bins by
+     * nnz(c_i); valid after spgemm_symbolic). */
+    int64_t sym_flop[9];
+    int64_t sym_probes[9];
+    int64_t num_flop[9];
+    int64_t num_probes[9];
 } spgemm_stats;
 
 int spgemm_plan_stats(spgemm_plan_t plan, int iprod, spgemm_stats *out);

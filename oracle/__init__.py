@@ -21,7 +21,9 @@ import numpy as np
 from synth.csr import CSR
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of spgemm_oracle.c (the sanitized one of the
+# sanitizer test); default: the in-tree liboracle.so
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 F64, I64 = 0, 1
@@ -38,6 +40,8 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
+        if "ORACLE_LIB" in os.environ:
+            raise FileNotFoundError(_LIB_PATH)
         build()
     lib = ctypes.CDLL(_LIB_PATH)
     p = ctypes.c_void_p

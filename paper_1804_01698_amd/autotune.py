@@ -19,8 +19,10 @@ HashVector variant, Section 4.2.2):
    of linear probing (Knuth) at the row's actual table load;
 3. the best-ranked candidates (and the defaults), and the best-ranked one
    and the defaults with 8- and 16-slot buckets, are timed end to end
-   through the library; the fastest per class is stored in a JSON file keyed
-   by device name and CU count.
+   through the library; for sorted output, so are both with the Heap
+   accumulator of Section 4.2.3 for the rows in its envelope (Eq. 1 prices
+   it at flop*log nnz(a_i)); the fastest per class is stored in a JSON file
+   keyed by device name and CU count.
 
 All timing runs the library's kernels; this module only chooses arguments.
 """
@@ -109,16 +111,6 @@ def prior_cost(flop: np.ndarray, key: np.ndarray, nnz: np.ndarray, cfg: dict, so
     return cost
 
 
-def row_stats(A, B) -> Tuple[np.ndarray, np.ndarray]:
-    """Row flop and key bound of C = A*B from the CSR structure (host)."""
-    degB = np.diff(np.asarray(B.rpts, dtype=np.int64))
-    per = degB[np.asarray(A.cols, dtype=np.int64)]
-    rp = np.asarray(A.rpts, dtype=np.int64)
-    flop = np.zeros(A.nrows, dtype=np.int64)
-    nz = np.diff(rp) > 0
-    if per.size:
-        flop[nz] = np.add.reduceat(per, rp[:-1][nz])
-    return flop, np.minimum(flop, B.ncols)
 
 
 # ---------------------------------------------------------------- timing
@@ -129,7 +121,10 @@ def _time_product(sp, dA, dB, sorted_output: bool, cfg: Optional[dict], reps: in
     for _ in range(reps + 1):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        p = sp.Plan([dA], [dB], sorted_output=sorted_output, config=cfg)
+        try:
+            p = sp.Plan([dA], [dB], sorted_output=sorted_output, config=cfg)
+        except sp.SpgemmError:
+            return math.inf                 # an arm the input does not admit (heap on unsorted B)
         p.symbolic()
         p.numeric()
         torch.cuda.synchronize()
@@ -150,8 +145,9 @@ def tune_class(sp, A, B, sorted_output: bool, top: int = 6, reps: int = 3) -> di
     p = sp.Plan([dA], [dB], sorted_output=sorted_output)
     p.symbolic()
     nnz = np.diff(p.rpts_C[0].cpu().numpy())
+    flop = p.row_flop(0).astype(np.int64)          # the library's row flop (Fig. 4 part 1)
     p.close()
-    flop, key = row_stats(A, B)
+    key = np.minimum(flop, B.ncols)
     default = sp.default_config()
     cands = []
     for sl in LOADS:
@@ -164,6 +160,8 @@ def tune_class(sp, A, B, sorted_output: bool, top: int = 6, reps: int = 3) -> di
     # best-ranked candidate are also timed with the 8- and 16-slot chunks
     arms = [(cands[0][0], dict(cands[0][1], bucket_slots=w)) for w in BUCKETS[1:]]
     arms += [(None, dict(default, bucket_slots=w)) for w in BUCKETS[1:]]
+    if sorted_output:
+        arms += [(None, dict(default, heap=1)), (cands[0][0], dict(cands[0][1], heap=1))]
     timed = [(None, default)] + [c for c in cands[:top]] + arms
     results = []
     for prior, cfg in timed:

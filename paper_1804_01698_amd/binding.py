@@ -13,7 +13,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libspgemm.so")
 
 F64, I64 = 0, 1
-SORTED, VALIDATE, TIMING, LOW_MEMORY = 1, 2, 4, 8
+SORTED, VALIDATE, TIMING, LOW_MEMORY, PROBE_COUNT = 1, 2, 4, 8, 16
+STATIC_WS_BYTES = 64 << 20          # SPGEMM_STATIC_WS_BYTES
+PLAN_HDR_BYTES = 512                # plan scratch: header, then uint32 row flop per row
+ERR_STATIC_LIMIT = -11
 
 
 def lib_path() -> str:
@@ -34,12 +37,14 @@ class _Csr(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("flop", ctypes.c_int64), ("max_row_flop", ctypes.c_int64), ("nnz_C", ctypes.c_int64),
                 ("heavy_rows", ctypes.c_int64), ("windows", ctypes.c_int64),
-                ("probe_overflow", ctypes.c_int64)]
+                ("probe_overflow", ctypes.c_int64), ("heap_rows", ctypes.c_int64),
+                ("sym_flop", ctypes.c_int64 * 9), ("sym_probes", ctypes.c_int64 * 9),
+                ("num_flop", ctypes.c_int64 * 9), ("num_probes", ctypes.c_int64 * 9)]
 
 
 class _Config(ctypes.Structure):
     _fields_ = [("hash_mul", ctypes.c_uint32), ("sym_max", ctypes.c_int32 * 9), ("num_max", ctypes.c_int32 * 9),
-                ("bucket_slots", ctypes.c_uint32)]
+                ("bucket_slots", ctypes.c_uint32), ("heap", ctypes.c_uint32)]
 
 
 class _KTime(ctypes.Structure):
@@ -181,7 +186,7 @@ def default_config() -> dict:
     c = _Config()
     _lib.spgemm_config_default(ctypes.byref(c))
     return {"hash_mul": int(c.hash_mul), "sym_max": list(c.sym_max), "num_max": list(c.num_max),
-            "bucket_slots": int(c.bucket_slots)}
+            "bucket_slots": int(c.bucket_slots), "heap": int(c.heap)}
 
 
 def _config_struct(cfg: Optional[dict]) -> Optional[_Config]:
@@ -193,6 +198,7 @@ def _config_struct(cfg: Optional[dict]) -> Optional[_Config]:
         c.sym_max[i] = int(cfg["sym_max"][i])
         c.num_max[i] = int(cfg["num_max"][i])
     c.bucket_slots = int(cfg.get("bucket_slots", 4))
+    c.heap = int(cfg.get("heap", 0))
     return c
 
 
@@ -209,7 +215,8 @@ class Plan:
 
     def __init__(self, As: Sequence[DeviceCSR], Bs: Sequence[DeviceCSR], sorted_output: bool = True,
                  dtype: Optional[int] = None, validate: bool = False, stream=None, timing: bool = False,
-                 defer_workspace: bool = False, config: Optional[dict] = None, low_memory: bool = False):
+                 defer_workspace: bool = False, config: Optional[dict] = None, low_memory: bool = False,
+                 probe_count: bool = False):
         if len(As) != len(Bs) or not As:
             raise ValueError("need equal, non-empty lists of operands")
         self.As, self.Bs = list(As), list(Bs)
@@ -226,7 +233,7 @@ class Plan:
             self.plan_scratch = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
         ws = ctypes.c_size_t(0)
         flags = ((SORTED if self.sorted else 0) | (VALIDATE if validate else 0) | (TIMING if timing else 0)
-                 | (LOW_MEMORY if low_memory else 0))
+                 | (LOW_MEMORY if low_memory else 0) | (PROBE_COUNT if probe_count else 0))
         cs = _config_struct(config)
         st = _lib.spgemm_plan(ctypes.byref(self._h), self.n, self._ca, self._cb, self.dtype, flags,
                               ctypes.c_void_p(self.plan_scratch.data_ptr()), _stream_handle(stream),
@@ -298,9 +305,20 @@ class Plan:
     def stats(self, i: int = 0) -> dict:
         s = _Stats()
         st = _lib.spgemm_plan_stats(self._h, i, ctypes.byref(s))
-        d = {f: int(getattr(s, f)) for f, _ in _Stats._fields_}
+        d = {}
+        for f, _ in _Stats._fields_:
+            v = getattr(s, f)
+            d[f] = [int(x) for x in v] if isinstance(v, ctypes.Array) else int(v)
         d["status"] = st
         return d
+
+    def row_flop(self, i: int = 0) -> np.ndarray:
+        """Row flop of product i as the plan computed it on the device (Fig. 4
+        part 1; uint32 per row, saturated at 2^32 - 1), copied to the host."""
+        off = sum(_lib.spgemm_plan_scratch_bytes(1, ctypes.byref(self._ca[j])) for j in range(i))
+        m = self.As[i].nrows
+        t = self.plan_scratch[off + PLAN_HDR_BYTES: off + PLAN_HDR_BYTES + 4 * m]
+        return t.view(torch.int32).cpu().numpy().view(np.uint32).copy()
 
     def kernel_times(self) -> List[dict]:
         buf = (_KTime * 64)()

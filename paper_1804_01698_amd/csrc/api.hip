@@ -60,7 +60,7 @@ struct Prod {
     size_t ws_base = 0, ws_bytes = 0;
     size_t o_hdr = 0, o_perm_sym = 0, o_perm_num = 0, o_nnz = 0, o_bsum = 0;
     size_t o_chunk = 0, o_heavy = 0, o_items = 0, o_bc = 0, o_bv = 0, o_long = 0;
-    size_t o_whist = 0, o_long_id = 0, o_idx = 0, o_slot = 0, o_bperm = 0, o_bmap = 0;
+    size_t o_whist = 0, o_long_id = 0, o_idx = 0, o_slot = 0, o_bperm = 0, o_bmap = 0, o_bs = 0;
     bool store_bm = false;    // symbolic bitmaps kept for the numeric windows
     // after symbolic
     char *ws = nullptr;
@@ -85,6 +85,7 @@ struct spgemm_plan_s {
     std::vector<Prod> prods;
     size_t ws_total = 0;
     bool timing = false;
+    uint32_t count_probes = 0;
     int ncu = 256;
     BinLimits lim = default_limits();
     std::vector<TimedLaunch> tl;
@@ -133,8 +134,10 @@ bool limits_from(const spgemm_config *cfg, BinLimits *L) {
     }
     if (L->sym[9] != WIN_CAP || L->num[9] != WIN_CAP) return false;
     if (cfg->bucket_slots != 4 && cfg->bucket_slots != 8 && cfg->bucket_slots != 16) return false;
+    if (cfg->heap > 1) return false;
     L->hmul = cfg->hash_mul;
     L->bq = cfg->bucket_slots / 4;
+    L->heap = cfg->heap;
     return true;
 }
 
@@ -204,6 +207,7 @@ void spgemm_config_default(spgemm_config *cfg) {
     if (!cfg) return;
     cfg->hash_mul = HASH_MUL_DEFAULT;
     cfg->bucket_slots = 4;
+    cfg->heap = 0;
     for (int b = 1; b <= 9; ++b) {
         cfg->sym_max[b - 1] = (int32_t)SYM_XMAX[b];
         cfg->num_max[b - 1] = (int32_t)NUM_XMAX[b];
@@ -222,7 +226,8 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     *out = nullptr;
     if (nprod <= 0 || !A || !B || !workspace_bytes) return SPGEMM_ERR_INVALID_ARG;
     if (dtype != SPGEMM_F64 && dtype != SPGEMM_I64) return SPGEMM_ERR_INVALID_ARG;
-    if (flags & ~(unsigned)(SPGEMM_SORTED | SPGEMM_VALIDATE | SPGEMM_TIMING | SPGEMM_LOW_MEMORY))
+    if (flags & ~(unsigned)(SPGEMM_SORTED | SPGEMM_VALIDATE | SPGEMM_TIMING | SPGEMM_LOW_MEMORY |
+                            SPGEMM_PROBE_COUNT))
         return SPGEMM_ERR_INVALID_ARG;
     for (int p = 0; p < nprod; ++p) {
         if (!csr_ok(A[p]) || !csr_ok(B[p])) return SPGEMM_ERR_INVALID_ARG;
@@ -231,6 +236,7 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     if (!plan_scratch) return SPGEMM_ERR_INVALID_ARG;
     BinLimits lim;
     if (!limits_from(cfg, &lim)) return SPGEMM_ERR_INVALID_ARG;
+    if (lim.heap && !(flags & SPGEMM_SORTED)) return SPGEMM_ERR_INVALID_ARG;   // the merge emits sorted rows
 
     spgemm_plan_s *pl = new (std::nothrow) spgemm_plan_s();
     if (!pl) return SPGEMM_ERR_HOST_ALLOC;
@@ -240,6 +246,7 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     pl->flags = flags;
     pl->stream = stream;
     pl->timing = (flags & SPGEMM_TIMING) != 0;
+    pl->count_probes = (flags & SPGEMM_PROBE_COUNT) ? 1u : 0u;
     {
         int devid = 0, ncu = 0;
         if (hipGetDevice(&devid) == hipSuccess &&
@@ -285,6 +292,7 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
         hipError_t e = timed(pl, "row_flop", 12.0 * q.A.nnz + 8.0 * q.m,
                              [&] { return launch_row_flop(q.A, q.B, q.flop, q.edeg, q.phdr, pl->lim, stream); });
         if (e == hipSuccess) e = launch_count_long_b(q.B, q.phdr, stream);
+        if (e == hipSuccess && pl->lim.heap) e = launch_check_sorted(q.B, &q.phdr->err, stream);
         if (e != hipSuccess) return fail(hip_fail(e, "row_flop"));
     }
     for (int p = 0; p < nprod; ++p) {
@@ -301,6 +309,7 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     for (int p = 0; p < nprod; ++p) {
         Prod &q = pl->prods[p];
         if (q.h.max_flop > (unsigned long long)INT32_MAX) return fail(SPGEMM_ERR_UNSUPPORTED);
+        if (pl->lim.heap && (q.h.err & ERR_UNSORTED_B)) return fail(SPGEMM_ERR_UNSUPPORTED);
         int64_t acc = 0;
         for (int b = 0; b < NSB; ++b) {
             q.sym_off[b] = acc;
@@ -337,6 +346,7 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
             q.o_whist = o; o += align_up(sizeof(uint32_t) * 2 * (size_t)q.nchunks);
             q.o_bperm = o; o += align_up(4 * (size_t)q.B.nnz);
             q.o_bc = o; o += align_up(4 * (size_t)q.B.nnz);
+            q.o_bs = o; o += align_up(4 * (size_t)q.B.nnz);
             q.o_bv = o; o += align_up(8 * (size_t)q.B.nnz);
             q.o_long = o; o += align_up(4 * (size_t)q.B.nrows);
             q.o_long_id = o; o += align_up(4 * (size_t)q.B.nrows);
@@ -379,6 +389,7 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
             HIPCK(timed(pl, "bucket_B", 8.0 * q.B.nrows + 16.0 * q.B.nnz,
                         [&] {
                             return launch_bucket(q.B, q.at<int32_t>(q.o_bc), q.at<int32_t>(q.o_bperm),
+                                                 q.at<int32_t>(q.o_bs),
                                                  q.at<int32_t>(q.o_long_id), q.at<int32_t>(q.o_long),
                                                  q.at<int32_t>(q.o_idx), q.nchunks, q.wh, s);
                         }),
@@ -390,9 +401,12 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
             if (nr == 0) continue;
             const double rows_bytes = 16.0 * nr + 12.0 * q.h.sym_nnza[b] + 4.0 * q.h.sym_flop[b];
             if (b == SYM_BITMAP_BIN) {
+                // B with every row in a scrambled order (see k_bucket_short)
+                CsrDev Bb = q.B;
+                Bb.cols = q.at<int32_t>(q.o_bs);
                 HIPCK(timed(pl, "sym_bitmap", rows_bytes + 4.0 * nr * q.nchunks,
                             [&] {
-                                return launch_sym_segments(nr, perm, off.v[b], q.A, q.B, q.nchunks,
+                                return launch_sym_segments(nr, perm, off.v[b], q.A, Bb, q.nchunks,
                                                            q.at<uint32_t>(q.o_chunk), nnz,
                                                            q.store_bm ? q.at<uint32_t>(q.o_bmap) : nullptr,
                                                            pl->ncu, s);
@@ -402,7 +416,9 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
                 char name[32];
                 snprintf(name, sizeof(name), "sym_hash_%d", SYM_T[b]);
                 HIPCK(timed(pl, name, rows_bytes,
-                            [&] { return launch_sym_bin(b, nr, perm, off.v[b], q.A, q.B, nnz, q.wh, HashCfg{pl->lim.hmul, pl->lim.bq}, pl->ncu, s); }),
+                            [&] { return launch_sym_bin(b, nr, perm, off.v[b], q.A, q.B, nnz, q.wh, 
+                                                              HashCfg{pl->lim.hmul, pl->lim.bq, pl->count_probes, (uint32_t)b},
+                                                              pl->ncu, s); }),
                       "sym_hash");
             }
         }
@@ -436,14 +452,14 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
         int64_t acc = 0;
         for (int b = 0; b < NNB; ++b) {
             q.num_off[b] = acc;
-            if (b > 0 && b < NUM_HEAVY_BIN) acc += (int64_t)q.hw.num_rows[b];
+            if (b > 0 && b != NUM_HEAVY_BIN) acc += (int64_t)q.hw.num_rows[b];
         }
         BinOffsets off{};
         for (int b = 0; b < NNB; ++b) off.v[b] = q.num_off[b];
         HIPCK(timed(pl, "num_scatter", 8.0 * q.m,
                     [&] {
-                        return launch_num_scatter((int)q.m, q.at<int32_t>(q.o_nnz), off, q.at<int32_t>(q.o_perm_num),
-                                                  q.wh, pl->lim, s);
+                        return launch_num_scatter((int)q.m, q.at<int32_t>(q.o_nnz), q.flop, q.A.rpts, off,
+                                                  q.at<int32_t>(q.o_perm_num), q.wh, pl->lim, s);
                     }),
               "num_scatter");
     }
@@ -504,9 +520,23 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
             HIPCK(timed(pl, name, bytes,
                         [&] {
                             return launch_num_bin(b, pl->dtype, sorted, nr, perm, q.num_off[b], q.A, q.B, q.rpts_C,
-                                                  cols_C[p], vals_C[p], q.wh, HashCfg{pl->lim.hmul, pl->lim.bq}, pl->ncu, s);
+                                                  cols_C[p], vals_C[p], q.wh,
+                                                  HashCfg{pl->lim.hmul, pl->lim.bq, pl->count_probes, (uint32_t)b},
+                                                  pl->ncu, s);
                         }),
                   "num_hash");
+        }
+        if (q.hw.num_rows[NUM_HEAP_BIN] > 0) {
+            const int hb = NUM_HEAP_BIN;
+            const unsigned nr = (unsigned)q.hw.num_rows[hb];
+            const double bytes = 28.0 * nr + 20.0 * q.hw.num_nnza[hb] + 12.0 * q.hw.num_flop[hb] +
+                                 12.0 * q.hw.num_nnzc[hb];
+            HIPCK(timed(pl, "num_heap", bytes,
+                        [&] {
+                            return launch_num_heap(pl->dtype, nr, perm, q.num_off[hb], q.A, q.B, q.rpts_C, cols_C[p],
+                                                   vals_C[p], q.wh, s);
+                        }),
+                  "num_heap");
         }
         if (nitems > 0) {
             const int hb = NUM_HEAVY_BIN;
@@ -542,6 +572,7 @@ int spgemm_plan_stats(spgemm_plan_t pl, int iprod, spgemm_stats *out) {
     memset(out, 0, sizeof(*out));
     out->flop = (int64_t)q.h.total_flop;
     out->max_row_flop = (int64_t)q.h.max_flop;
+    for (int b = 1; b <= 9; ++b) out->sym_flop[b - 1] = (int64_t)q.h.sym_flop[b];
     if (pl->state >= SYMBOLIC_DONE) {
         WsHdr now{};
         HIPCK(hipMemcpyAsync(&now, q.wh, sizeof(WsHdr), hipMemcpyDeviceToHost, pl->stream), "stats readback");
@@ -550,6 +581,12 @@ int spgemm_plan_stats(spgemm_plan_t pl, int iprod, spgemm_stats *out) {
         out->heavy_rows = (int64_t)now.n_heavy;
         out->windows = (int64_t)now.n_items;
         out->probe_overflow = (int64_t)now.probe_overflow;
+        out->heap_rows = (int64_t)now.num_rows[NUM_HEAP_BIN];
+        for (int b = 1; b <= 9; ++b) {
+            out->num_flop[b - 1] = (int64_t)now.num_flop[b];
+            out->num_probes[b - 1] = (int64_t)now.num_probes[b];
+            out->sym_probes[b - 1] = (int64_t)now.sym_probes[b];
+        }
         if (now.err & ~ERR_PROBE) return SPGEMM_ERR_INTERNAL;
         if (now.probe_overflow) return SPGEMM_ERR_INTERNAL;
     }

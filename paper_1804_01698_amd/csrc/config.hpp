@@ -17,8 +17,12 @@ constexpr int WIN_CAP = 8448;      // load factor <= 0.75
 // A column window of a heavy row holds, in LDS, one 64-bit word per 32
 // columns (occupancy bits + exclusive rank prefix), one value per output
 // entry and a 4-byte staging slot per entry: 128 words per chunk plus 1.5
-// words per entry must fit RANK_BUDGET words.
+// words per entry must fit RANK_BUDGET words.  Windows are worked on by
+// blocks of WIN_G threads, one per CU (the LDS of two blocks of 512 threads
+// with half the budget each measured 3 % slower at R-MAT scale 20: twice the
+// windows, and more rows above the block's resident A entries).
 constexpr int WORDS_PER_CHUNK = CHUNK_COLS / 32;
+constexpr int WIN_G = 1024;
 constexpr int RANK_BUDGET = 17664;
 constexpr int MAX_CHUNKS = 32768;  // heavy-row support: ncols <= 2^27
 // B rows longer than SHORT_ROW get a chunk-offset index (slice of a window =
@@ -44,12 +48,17 @@ constexpr int SYM_T[NSB] = {0, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384,
 constexpr int64_t SYM_XMAX[NSB] = {0, 32, 64, 128, 256, 512, 1024, 2048, 4096, WIN_CAP, INT64_MAX};
 
 // Numeric bins by exact nnz(c_i): bin 0 = empty row, bins 1..9 LDS hash
-// tables of keys+values, bin 10 = heavy (column windows).
-constexpr int NNB = 11;
+// tables of keys+values, bin 10 = heavy (column windows), bin 11 = heap merge
+// (only when a plan asks for it: rows of bins 1..9 with at most HEAP_MAX_A
+// entries of A and at most HEAP_FCAP products).
+constexpr int NNB = 12;
 constexpr int NUM_HEAVY_BIN = 10;
-constexpr int NUM_G[NNB] = {0, 64, 64, 64, 64, 128, 256, 512, 1024, 1024, 1024};
-constexpr int NUM_T[NNB] = {0, 64, 128, 256, 512, 1024, 2048, 4096, 8192, WIN_TABLE, WIN_TABLE};
-constexpr int64_t NUM_XMAX[NNB] = {0, 32, 64, 128, 256, 512, 1024, 2048, 4096, WIN_CAP, INT64_MAX};
+constexpr int NUM_HEAP_BIN = 11;
+constexpr int HEAP_MAX_A = 256;
+constexpr int HEAP_FCAP = 1024;
+constexpr int NUM_G[NNB] = {0, 64, 64, 64, 64, 128, 256, 512, 1024, 1024, 1024, 64};
+constexpr int NUM_T[NNB] = {0, 64, 128, 256, 512, 1024, 2048, 4096, 8192, WIN_TABLE, WIN_TABLE, 0};
+constexpr int64_t NUM_XMAX[NNB] = {0, 32, 64, 128, 256, 512, 1024, 2048, 4096, WIN_CAP, INT64_MAX, 0};
 
 // Bin limits of one plan (tunable; see spgemm_config): bin b of the symbolic
 // phase takes rows with sym[b-1] < min(flop, ncols) <= sym[b], bin b of the
@@ -58,19 +67,23 @@ constexpr int64_t NUM_XMAX[NNB] = {0, 32, 64, 128, 256, 512, 1024, 2048, 4096, W
 // WIN_CAP in both phases (the heavy-row boundary is structural).  hmul is
 // the odd multiplier of the column hash, bq the 4-slot quads per bucket of
 // the LDS tables (1: 4-slot buckets; 2 or 4: the wider chunks of the
-// paper's HashVector, Section 4.2.2).
+// paper's HashVector, Section 4.2.2); heap = 1 sends the numeric phase of the
+// rows in the heap envelope to the heap merge (Section 4.2.3).
 constexpr uint32_t HASH_MUL_DEFAULT = 2654435761u;
 struct BinLimits {
     int64_t sym[NSB];
     int64_t num[NNB];
     uint32_t hmul;
     uint32_t bq;
+    uint32_t heap;
 };
 
 // What a hash kernel needs of the configuration.
 struct HashCfg {
     uint32_t mul;   // odd multiplier of the column hash
     uint32_t bq;    // 4-slot quads per bucket: 1, 2 or 4
+    uint32_t count; // 1: add the bucket reads of every insert to the bin's probe counter
+    uint32_t bin;   // the kernel's bin (index of that counter)
 };
 
 __host__ __device__ inline BinLimits default_limits() {
@@ -79,6 +92,7 @@ __host__ __device__ inline BinLimits default_limits() {
     for (int b = 0; b < NNB; ++b) L.num[b] = NUM_XMAX[b];
     L.hmul = HASH_MUL_DEFAULT;
     L.bq = 1;
+    L.heap = 0;
     return L;
 }
 
@@ -95,6 +109,14 @@ __host__ __device__ inline int num_bin_l(int64_t nnz, const BinLimits &L) {
     for (int b = 1; b < NUM_HEAVY_BIN; ++b)
         if (nnz <= L.num[b]) return b;
     return NUM_HEAVY_BIN;
+}
+
+// Numeric bin of a row with nnz(c_i) = nnz, row flop and na entries of A.
+__host__ __device__ inline int num_bin_row(int64_t nnz, uint64_t flop, int na, const BinLimits &L) {
+    const int b = num_bin_l(nnz, L);
+    if (L.heap && b >= 1 && b < NUM_HEAVY_BIN && na <= HEAP_MAX_A && flop <= (uint64_t)HEAP_FCAP)
+        return NUM_HEAP_BIN;
+    return b;
 }
 
 __host__ __device__ inline int sym_bin(uint64_t flop, int64_t ncols) {
@@ -124,7 +146,8 @@ enum : int {
     ERR_COUNT = 2,       // numeric row count differs from the symbolic count
     ERR_ITEMS = 4,       // window item list capacity exceeded
     ERR_CSR = 8,         // malformed CSR (validate mode)
-    ERR_CHUNK = 16       // a heavy row has a chunk wider than a window
+    ERR_CHUNK = 16,      // a heavy row has a chunk wider than a window
+    ERR_UNSORTED_B = 32  // a row of B is not in ascending column order
 };
 
 struct PlanHdr {
@@ -154,6 +177,8 @@ struct WsHdr {
     unsigned int n_groups;
     unsigned int pad2_[2];
     unsigned int win_next[8];   // window claim counters, one per XCD group
+    unsigned long long sym_probes[NSB];   // bucket reads of the hash inserts (SPGEMM_PROBE_COUNT)
+    unsigned long long num_probes[NNB];
 };
 
 // One column window of one heavy row.

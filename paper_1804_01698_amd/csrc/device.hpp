@@ -154,9 +154,12 @@ __device__ __forceinline__ int bucket_pick(int4 k, int key, bool &empty_hit) {
 // that runs past every bucket without room sets ovf and gives up.
 // FIXED_BQ > 0 fixes bq at compile time (the default 4-slot buckets compile
 // to the plain one-quad probe).
+// *probes (if given) counts the quads read: the collision factor of Eq. 2 is
+// their number per insertion.
 template <bool NUM, typename V, int FIXED_BQ = 0>
 __device__ __forceinline__ int bkt_insert(int *keys, V *vals, uint32_t T, int key, V x, int &ovf,
-                                          uint32_t mul = HASH_MUL_DEFAULT, uint32_t bq_rt = 1) {
+                                          uint32_t mul = HASH_MUL_DEFAULT, uint32_t bq_rt = 1,
+                                          unsigned *probes = nullptr) {
     const uint32_t bq = FIXED_BQ > 0 ? (uint32_t)FIXED_BQ : bq_rt;
     const uint32_t W = BKT * bq;                   // slots per bucket
     const uint32_t NB = T / W;
@@ -166,6 +169,7 @@ __device__ __forceinline__ int bkt_insert(int *keys, V *vals, uint32_t T, int ke
         __asm__ __volatile__("" ::: "memory");   // re-read the quad every round
         const uint32_t base = b * W + q * BKT;
         const int4 k = lds_load4(&keys[base]);
+        if (probes) ++*probes;
         bool e;
         const int j = bucket_pick(k, key, e);
         if (j < 0) {                               // quad full without the key

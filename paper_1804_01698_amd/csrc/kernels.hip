@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_num_hist(int m, const int32_t *__restri
     const int i = blockIdx.x * 256 + tid;
     if (i < m) {
         const int nz = nnz_row[i];
-        const int b = num_bin_l(nz, L);
+        const int b = num_bin_row(nz, flop[i], rA[i + 1] - rA[i], L);
         atomicAdd(&s_rows[b], 1ull);
         atomicAdd(&s_flop[b], (unsigned long long)flop[i]);
         atomicAdd(&s_nnza[b], (unsigned long long)(rA[i + 1] - rA[i]));
@@ -199,6 +199,8 @@ __global__ __launch_bounds__(256) void k_num_hist(int m, const int32_t *__restri
 }
 
 __global__ __launch_bounds__(256) void k_num_scatter(int m, const int32_t *__restrict__ nnz_row,
+                                                     const uint32_t *__restrict__ flop,
+                                                     const int32_t *__restrict__ rA,
                                                      BinOffsets off, int32_t *__restrict__ perm,
                                                      WsHdr *wh, BinLimits L) {
     __shared__ unsigned int s_cnt[NNB], s_base[NNB];
@@ -209,8 +211,8 @@ __global__ __launch_bounds__(256) void k_num_scatter(int m, const int32_t *__res
     int b = -1;
     unsigned int r = 0;
     if (i < m) {
-        b = num_bin_l(nnz_row[i], L);
-        if (b > 0 && b < NUM_HEAVY_BIN) r = atomicAdd(&s_cnt[b], 1u);
+        b = num_bin_row(nnz_row[i], flop[i], rA[i + 1] - rA[i], L);
+        if (b > 0 && b != NUM_HEAVY_BIN) r = atomicAdd(&s_cnt[b], 1u);
         else b = -1;
     }
     __syncthreads();
@@ -288,6 +290,7 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
         if constexpr (PERSIST)
             if (nit < nrows) nxt = row_pre_entry<G, false, double>(perm[perm_off + nit], rA, cA, nullptr);
         int cnt = 0, ovf = 0;
+        unsigned prb = 0;
         auto act = [&](const int (&q)[U], const bool (&ok)[U], const double (&)[U]) {
             int col[U];
 #pragma unroll
@@ -298,11 +301,11 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
             if (hc.bq == 1) {
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (ok[u]) cnt += bkt_insert<false, double, 1>(tab, nullptr, T, col[u], 0.0, ovf, hc.mul);
+                    if (ok[u]) cnt += bkt_insert<false, double, 1>(tab, nullptr, T, col[u], 0.0, ovf, hc.mul, 1u, &prb);
             } else {
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hc.mul, hc.bq);
+                    if (ok[u]) cnt += bkt_insert<false, double>(tab, nullptr, T, col[u], 0.0, ovf, hc.mul, hc.bq, &prb);
             }
         };
         auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
@@ -315,6 +318,10 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
         int total;
         block_excl_scan<G, int>(cnt, total, sg.wsum);
         if (tid == 0) nnz_row[row] = total;
+        if (hc.count) {
+            const unsigned long long t = wave_sum_u64(prb);
+            if ((tid & 63) == 0 && t) atomicAdd(&wh->sym_probes[hc.bin], t);
+        }
         if (ovf) {
             atomicAdd(&wh->probe_overflow, 1u);
             atomicOr(&wh->err, ERR_PROBE);
@@ -649,12 +656,32 @@ __global__ __launch_bounds__(1024) void k_win_emit(const HeavyRow *__restrict__ 
 
 // ----------------------------------------------------------------------- bucket B by chunk
 
-// Rows of at most SHORT_ROW entries keep their order (windows read them whole
-// and filter by column); longer rows are listed for k_bucket_long.  bperm[p]
-// is the original position of the entry now at p (values follow in numeric).
+// Multiplier of the scrambled order of a row of len > 1 entries: odd, near
+// len times the golden ratio's fractional part, coprime to len, so that
+// t -> t*K mod len is a permutation that sends neighbours far apart.
+__device__ inline int scramble_mul(int len) {
+    int k = (int)((double)len * 0.6180339887498949) | 1;
+    for (;; k += 2) {
+        if (k >= len) return 1;
+        int a = len, b = k;
+        while (b) { const int t = a % b; a = b; b = t; }
+        if (a == 1) return k;
+    }
+}
+
+// Besides the bucketed copy, every row of B is also written in a scrambled
+// order (bs: entry t of the row goes to position t*K mod len).  The symbolic
+// bitmap reads that copy: consecutive lanes then carry columns from all over
+// the row even when the input rows are sorted, so the LDS atomic ORs of a
+// wave rarely meet in one word.
+// Rows of at most SHORT_ROW entries keep their order in bc (windows read them
+// whole and filter by column); longer rows are listed for k_bucket_long.
+// bperm[p] is the original position of the entry now at p of bc (values
+// follow in numeric).
 __global__ __launch_bounds__(256) void k_bucket_short(int n, const int32_t *__restrict__ rB,
                                                       const int32_t *__restrict__ cB,
                                                       int32_t *__restrict__ bc, int32_t *__restrict__ bperm,
+                                                      int32_t *__restrict__ bs,
                                                       int32_t *__restrict__ long_id,
                                                       int32_t *__restrict__ long_list, WsHdr *wh) {
     const int row = blockIdx.x * 256 + (int)threadIdx.x;
@@ -667,31 +694,54 @@ __global__ __launch_bounds__(256) void k_bucket_short(int n, const int32_t *__re
         return;
     }
     long_id[row] = -1;
+    const int len = b1 - b0;
+    const int K = len > 1 ? scramble_mul(len) : 1;
+    int j = 0;
     for (int p = b0; p < b1; ++p) {
-        bc[p] = cB[p];
+        const int c = cB[p];
+        bc[p] = c;
         bperm[p] = p;
+        bs[b0 + j] = c;
+        j += K;
+        if (j >= len) j -= len;
     }
 }
 
 // Longer rows: counting sort by chunk id with LDS counters, and the chunk
 // offsets (relative to the row start) kept as the row's index:
 // idx[li*(nchunks+1) + c] = first position of chunk c, idx[..+nchunks] = len.
+// The counting pass also writes the row's scrambled copy into bs.
 template <int NCNT>
 __global__ __launch_bounds__(256) void k_bucket_long(const int32_t *__restrict__ long_list,
                                                      const WsHdr *wh, const int32_t *__restrict__ rB,
                                                      const int32_t *__restrict__ cB,
                                                      int32_t *__restrict__ bc, int32_t *__restrict__ bperm,
+                                                     int32_t *__restrict__ bs,
                                                      int32_t *__restrict__ idx, int nchunks) {
     __shared__ int cnt[NCNT];
     __shared__ int ws[5];
+    __shared__ int s_k;
     const int tid = threadIdx.x;
     const unsigned nl = wh->n_long;
     for (unsigned li = blockIdx.x; li < nl; li += gridDim.x) {
         const int row = long_list[li];
         const int b0 = rB[row], b1 = rB[row + 1];
+        const int len = b1 - b0;
         for (int c = tid; c < nchunks; c += 256) cnt[c] = 0;
+        if (tid == 0) s_k = scramble_mul(len);
         __syncthreads();
-        for (int p = b0 + tid; p < b1; p += 256) atomicAdd(&cnt[cB[p] >> CHUNK_SHIFT], 1);
+        {
+            const int K = s_k;
+            const int jstep = (int)(((int64_t)256 * K) % len);
+            int j = (int)(((int64_t)tid * K) % len);
+            for (int p = b0 + tid; p < b1; p += 256) {
+                const int col = cB[p];
+                atomicAdd(&cnt[col >> CHUNK_SHIFT], 1);
+                bs[b0 + j] = col;
+                j += jstep;
+                if (j >= len) j -= len;
+            }
+        }
         __syncthreads();
         int32_t *ix = idx + (size_t)li * (nchunks + 1);
         int carry = 0;
@@ -706,7 +756,7 @@ __global__ __launch_bounds__(256) void k_bucket_long(const int32_t *__restrict__
             }
             carry += tot;
         }
-        if (tid == 0) ix[nchunks] = b1 - b0;
+        if (tid == 0) ix[nchunks] = len;
         __syncthreads();
         for (int p = b0 + tid; p < b1; p += 256) {
             const int col = cB[p];
@@ -776,6 +826,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
         if constexpr (PERSIST)
             if (nit < nrows) nxt = row_pre_entry<G, true, V>(perm[perm_off + nit], rA, cA, vA);
         int ovf = 0;
+        unsigned prb = 0;
         auto act = [&](const int (&q)[U], const bool (&ok)[U], const V (&av)[U]) {
             int col[U];
             V x[U];
@@ -789,11 +840,11 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
             if (hc.bq == 1) {
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (ok[u]) bkt_insert<true, V, 1>(keys, vals, T, col[u], x[u], ovf, hc.mul);
+                    if (ok[u]) bkt_insert<true, V, 1>(keys, vals, T, col[u], x[u], ovf, hc.mul, 1u, &prb);
             } else {
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf, hc.mul, hc.bq);
+                    if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], x[u], ovf, hc.mul, hc.bq, &prb);
             }
         };
         auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
@@ -806,6 +857,10 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
         if (ovf) {
             atomicAdd(&wh->probe_overflow, 1u);
             atomicOr(&wh->err, ERR_PROBE);
+        }
+        if (hc.count) {
+            const unsigned long long t = wave_sum_u64(prb);
+            if ((tid & 63) == 0 && t) atomicAdd(&wh->num_probes[hc.bin], t);
         }
         const int64_t o = rpts_C[row];
         const int expected = (int)(rpts_C[row + 1] - o);
@@ -924,7 +979,7 @@ constexpr int WIN_PRE_WORDS = 3;
 // latency hides behind loads the window waits for anyway.  Output stores are
 // left in flight (a block barrier does not wait for stores).
 template <typename V>
-__global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__ items, unsigned nitems,
+__global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict__ items, unsigned nitems,
                                                      const int32_t *__restrict__ cA,
                                                      const V *__restrict__ vA,
                                                      const int32_t *__restrict__ rB,
@@ -934,7 +989,7 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
                                                      const V *__restrict__ bv,
                                                      int32_t *__restrict__ cC, V *__restrict__ vC,
                                                      const uint32_t *__restrict__ bmap, WsHdr *wh) {
-    constexpr int G = 1024;
+    constexpr int G = WIN_G;
     __shared__ __align__(16) unsigned long long buf[RANK_BUDGET];   // words, then values
     __shared__ SegLds<G, true, V> sg;
     __shared__ unsigned s_claim[2];
@@ -1129,6 +1184,157 @@ __global__ __launch_bounds__(1024) void k_num_window(const WinItem *__restrict__
         par ^= 1;
     }
     if (bad) atomicOr(&wh->err, ERR_COUNT);
+}
+
+// ----------------------------------------------------------------------- heap merge
+
+// Wave-wide reductions (every lane active).
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_add_f64(double);
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
+
+__device__ __forceinline__ int wave_min_all(int x) { return __ockl_wfred_min_i32(x); }
+__device__ __forceinline__ double wave_add_all(double x) { return __ockl_wfred_add_f64(x); }
+__device__ __forceinline__ unsigned long long wave_add_all(unsigned long long x) {
+    return __ockl_wfred_add_u64(x);
+}
+
+// Rows of B in ascending column order (repeats allowed)?  Sets ERR_UNSORTED_B
+// in *err otherwise.
+__global__ __launch_bounds__(256) void k_check_sorted(int64_t nnz, const int32_t *__restrict__ rB,
+                                                      int64_t nrows, const int32_t *__restrict__ cB, int *err) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    bool bad = false;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < nrows; r += stride) {
+        const int b0 = rB[r], b1 = rB[r + 1];
+        for (int p = b0 + 1; p < b1; ++p) bad |= cB[p] < cB[p - 1];
+    }
+    (void)nnz;
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(err, ERR_UNSORTED_B);
+}
+
+// Numeric phase of the heap bin: the priority-queue accumulation of Section
+// 4.2.3.  Row c_i is built by repeatedly taking the smallest column among the
+// heads of the B rows that the entries a_ik select, adding a_ik*b_kj for every
+// head at that column, and advancing those heads; the queue holds one head
+// per entry of a_i (O(nnz(a_i)) state, as in the paper).  On the GPU a row is
+// one wave: the row's B slices (at most HEAP_FCAP products) are first copied
+// to LDS, lane l keeps the heads of the row's entries l, l+64, l+128, l+192
+// (a four-slot queue per lane), and the queue's minimum is the wave-wide
+// minimum of the lanes' smallest heads (a tournament over the 64 lanes in
+// cross-lane reductions).  A column met again in the next round (a repeated
+// column inside a B row, or a repeated k) adds into the same entry.  Entries
+// leave in ascending column order, 64 per coalesced store.  The B rows must be
+// sorted (checked when the plan is made).
+template <typename V>
+__global__ __launch_bounds__(64) void k_num_heap(const int32_t *__restrict__ perm, int64_t perm_off, unsigned nrows,
+                                                 const int32_t *__restrict__ rA, const int32_t *__restrict__ cA,
+                                                 const V *__restrict__ vA, const int32_t *__restrict__ rB,
+                                                 const int32_t *__restrict__ cB, const V *__restrict__ vB,
+                                                 const int64_t *__restrict__ rpts_C, int32_t *__restrict__ cC,
+                                                 V *__restrict__ vC, WsHdr *wh) {
+    constexpr int NQ = HEAP_MAX_A / WAVE;       // queue slots per lane
+    constexpr int NONE = 0x7FFFFFFF;            // head of an exhausted slice
+    __shared__ int scol[HEAP_FCAP];
+    __shared__ V sval[HEAP_FCAP];
+    __shared__ int soff[HEAP_MAX_A];
+    __shared__ int slo[HEAP_MAX_A];
+    const int ln = threadIdx.x;
+    if (blockIdx.x >= nrows) return;
+    const int row = perm[perm_off + blockIdx.x];
+    const int a0 = rA[row], a1 = rA[row + 1];
+    // the slices of the row's entries, laid end to end in LDS (entry a0 + s
+    // owns positions [soff[s], soff[s] + len))
+    int cur[NQ], end[NQ];
+    V av[NQ];
+    int base = 0;
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+        const int e = a0 + t * WAVE + ln;
+        int lo = 0, len = 0;
+        av[t] = V(0);
+        if (e < a1) {
+            const int k = cA[e];
+            av[t] = vA[e];
+            lo = rB[k];
+            len = rB[k + 1] - lo;
+        }
+        const int incl = wave_incl_scan<int>(len);
+        cur[t] = base + incl - len;
+        end[t] = base + incl;
+        soff[t * WAVE + ln] = cur[t];
+        slo[t * WAVE + ln] = lo;
+        base += __shfl(incl, WAVE - 1);
+    }
+    const int F = base;                         // <= HEAP_FCAP (the bin's rule)
+    wave_sync();
+    for (int p = ln; p < F; p += WAVE) {
+        int l = 0, h = HEAP_MAX_A - 1;          // the last slice starting at or before p
+        while (l < h) {
+            const int mid = (l + h + 1) >> 1;
+            if (soff[mid] <= p) l = mid; else h = mid - 1;
+        }
+        const int src = slo[l] + (p - soff[l]);
+        scol[p] = cB[src];
+        sval[p] = vB[src];
+    }
+    wave_sync();
+    int head[NQ];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) head[t] = cur[t] < end[t] ? scol[cur[t]] : NONE;
+    const int64_t o = rpts_C[row];
+    const int expected = (int)(rpts_C[row + 1] - o);
+    int nout = 0;                               // entries emitted (wave-uniform)
+    int last = -1;                              // column of the pending entry (wave-uniform)
+    V pend = V(0);
+    int rc = 0;                                 // this lane's slot of the 64-entry output run
+    V rv = V(0);
+    auto emit = [&](int c, V v) {
+        if (ln == (nout & (WAVE - 1))) {
+            rc = c;
+            rv = v;
+        }
+        ++nout;
+        if ((nout & (WAVE - 1)) == 0) {
+            const int at = nout - WAVE + ln;
+            if (at < expected) {
+                __builtin_nontemporal_store(rc, &cC[o + at]);
+                __builtin_nontemporal_store(rv, &vC[o + at]);
+            }
+        }
+    };
+    for (;;) {
+        int lm = head[0];
+#pragma unroll
+        for (int t = 1; t < NQ; ++t) lm = min(lm, head[t]);
+        const int m = wave_min_all(lm);
+        if (m == NONE) break;
+        V x = V(0);
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+            if (head[t] == m) {
+                x += av[t] * sval[cur[t]];
+                ++cur[t];
+                head[t] = cur[t] < end[t] ? scol[cur[t]] : NONE;
+            }
+        const V sum = wave_add_all(x);
+        if (m == last) {
+            pend += sum;
+        } else {
+            if (last >= 0) emit(last, pend);
+            last = m;
+            pend = sum;
+        }
+    }
+    if (last >= 0) emit(last, pend);
+    const int rem = nout & (WAVE - 1);
+    if (rem) {
+        const int at = nout - rem + ln;
+        if (ln < rem && at < expected) {
+            __builtin_nontemporal_store(rc, &cC[o + at]);
+            __builtin_nontemporal_store(rv, &vC[o + at]);
+        }
+    }
+    if (nout != expected && ln == 0) atomicOr(&wh->err, ERR_COUNT);
 }
 
 // ----------------------------------------------------------------------- masked product sum
@@ -1456,15 +1662,15 @@ hipError_t launch_windows(unsigned nheavy_max, const HeavyRow *heavy, int nchunk
     return hipGetLastError();
 }
 
-hipError_t launch_bucket(const CsrDev &B, int32_t *bc, int32_t *bperm, int32_t *long_id, int32_t *long_list,
-                         int32_t *idx, int nchunks, WsHdr *wh, hipStream_t s) {
+hipError_t launch_bucket(const CsrDev &B, int32_t *bc, int32_t *bperm, int32_t *bs, int32_t *long_id,
+                         int32_t *long_list, int32_t *idx, int nchunks, WsHdr *wh, hipStream_t s) {
     if (B.nrows == 0) return hipSuccess;
-    k_bucket_short<<<grid1(B.nrows, 256), 256, 0, s>>>((int)B.nrows, B.rpts, B.cols, bc, bperm, long_id, long_list,
-                                                        wh);
+    k_bucket_short<<<grid1(B.nrows, 256), 256, 0, s>>>((int)B.nrows, B.rpts, B.cols, bc, bperm, bs, long_id,
+                                                        long_list, wh);
     if (nchunks <= 1024)
-        k_bucket_long<1024><<<4096, 256, 0, s>>>(long_list, wh, B.rpts, B.cols, bc, bperm, idx, nchunks);
+        k_bucket_long<1024><<<4096, 256, 0, s>>>(long_list, wh, B.rpts, B.cols, bc, bperm, bs, idx, nchunks);
     else
-        k_bucket_long<MAX_CHUNKS><<<1024, 256, 0, s>>>(long_list, wh, B.rpts, B.cols, bc, bperm, idx, nchunks);
+        k_bucket_long<MAX_CHUNKS><<<1024, 256, 0, s>>>(long_list, wh, B.rpts, B.cols, bc, bperm, bs, idx, nchunks);
     return hipGetLastError();
 }
 
@@ -1477,10 +1683,10 @@ hipError_t launch_gather_vals(int dtype, int64_t n, const int32_t *bperm, const 
     return hipGetLastError();
 }
 
-hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &off, int32_t *perm, WsHdr *wh,
-                              const BinLimits &L, hipStream_t s) {
+hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
+                              const BinOffsets &off, int32_t *perm, WsHdr *wh, const BinLimits &L, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    k_num_scatter<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, off, perm, wh, L);
+    k_num_scatter<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, flop, rA, off, perm, wh, L);
     return hipGetLastError();
 }
 
@@ -1542,18 +1748,38 @@ hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, c
     if (nitems == 0) return hipSuccess;
     k_zero_u32n<<<1, 64, 0, s>>>(wh->win_next, 8);
     if (dtype == 0) {
-        static const int occ = blocks_per_cu(k_num_window<double>, 1024);
+        static const int occ = blocks_per_cu(k_num_window<double>, WIN_G);
         const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
-        k_num_window<double><<<grid, 1024, 0, s>>>(items, nitems, A.cols, (const double *)A.vals, B.rpts, long_id,
+        k_num_window<double><<<grid, WIN_G, 0, s>>>(items, nitems, A.cols, (const double *)A.vals, B.rpts, long_id,
                                                    idx, nchunks, bc, (const double *)bv, cC, (double *)vC, bmap,
                                                    wh);
     } else {
-        static const int occ = blocks_per_cu(k_num_window<unsigned long long>, 1024);
+        static const int occ = blocks_per_cu(k_num_window<unsigned long long>, WIN_G);
         const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
-        k_num_window<unsigned long long><<<grid, 1024, 0, s>>>(
+        k_num_window<unsigned long long><<<grid, WIN_G, 0, s>>>(
             items, nitems, A.cols, (const unsigned long long *)A.vals, B.rpts, long_id, idx, nchunks, bc,
             (const unsigned long long *)bv, cC, (unsigned long long *)vC, bmap, wh);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_check_sorted(const CsrDev &B, int *err, hipStream_t s) {
+    if (B.nrows == 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>(grid1(B.nrows, 256), 8192);
+    k_check_sorted<<<g, 256, 0, s>>>(B.nnz, B.rpts, B.nrows, B.cols, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_num_heap(int dtype, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
+                           const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s) {
+    if (nrows == 0) return hipSuccess;
+    if (dtype == 0)
+        k_num_heap<double><<<nrows, WAVE, 0, s>>>(perm, off, nrows, A.rpts, A.cols, (const double *)A.vals, B.rpts,
+                                                  B.cols, (const double *)B.vals, rpts_C, cC, (double *)vC, wh);
+    else
+        k_num_heap<unsigned long long><<<nrows, WAVE, 0, s>>>(
+            perm, off, nrows, A.rpts, A.cols, (const unsigned long long *)A.vals, B.rpts, B.cols,
+            (const unsigned long long *)B.vals, rpts_C, cC, (unsigned long long *)vC, wh);
     return hipGetLastError();
 }
 

@@ -40,11 +40,14 @@ hipError_t launch_count_long_b(const CsrDev &B, PlanHdr *hdr, hipStream_t s);
 hipError_t launch_windows(unsigned nheavy_max, const HeavyRow *heavy, int nchunks, const uint32_t *chunk_cnt,
                           const int64_t *rpts_C, const int32_t *rA, uint32_t *whist, uint32_t *wcur, WinItem *items,
                           unsigned cap, WsHdr *wh, hipStream_t s);
-hipError_t launch_bucket(const CsrDev &B, int32_t *bc, int32_t *bperm, int32_t *long_id, int32_t *long_list,
-                         int32_t *idx, int nchunks, WsHdr *wh, hipStream_t s);
+hipError_t launch_bucket(const CsrDev &B, int32_t *bc, int32_t *bperm, int32_t *bs, int32_t *long_id,
+                         int32_t *long_list, int32_t *idx, int nchunks, WsHdr *wh, hipStream_t s);
 hipError_t launch_gather_vals(int dtype, int64_t n, const int32_t *bperm, const void *vB, void *bv, hipStream_t s);
-hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const BinOffsets &off, int32_t *perm, WsHdr *wh,
-                              const BinLimits &L, hipStream_t s);
+hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
+                              const BinOffsets &off, int32_t *perm, WsHdr *wh, const BinLimits &L, hipStream_t s);
+hipError_t launch_check_sorted(const CsrDev &B, int *err, hipStream_t s);
+hipError_t launch_num_heap(int dtype, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
+                           const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s);
 hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
                           const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
                           WsHdr *wh, HashCfg hc, int ncu, hipStream_t s);

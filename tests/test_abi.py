@@ -61,6 +61,12 @@ def test_host_side_argument_errors(lib):
     st = lib.spgemm_plan(ctypes.byref(h), 1, ctypes.byref(A), ctypes.byref(B2), 0, 0,
                          ctypes.c_void_p(1), None, ctypes.byref(ws), ctypes.byref(bad))
     assert st == -1 and not h.value               # invalid config, rejected before any device work
+    heap = b._config_struct(dict(b.default_config(), heap=1))
+    st = lib.spgemm_plan(ctypes.byref(h), 1, ctypes.byref(A), ctypes.byref(B2), 0, 0,
+                         ctypes.c_void_p(1), None, ctypes.byref(ws), ctypes.byref(heap))
+    assert st == -1 and not h.value               # the heap merge needs sorted output
+    assert lib.spgemm_symbolic_static(None, None, None) == -1
+    assert b"static scratch" in lib.spgemm_strerror(-11)
     assert lib.spgemm_symbolic(None, None, None, None) == -1
     assert lib.spgemm_stream_copy(None, None, 15, None) == -1
     one = ctypes.c_void_p(8)                      # never dereferenced: every call below is rejected first

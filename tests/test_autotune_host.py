@@ -31,14 +31,11 @@ def test_default_config_is_the_half_load_candidate():
     assert c["sym_max"][:8] == d["sym_max"][:8] and c["num_max"][:8] == d["num_max"][:8]
 
 
-def test_row_stats_matches_definition():
-    A = random_sparse(40, 30, 0.2, 3)
-    B = random_sparse(30, 50, 0.1, 4)
-    flop, key = at.row_stats(A, B)
-    degB = np.diff(B.rpts)
-    want = np.array([degB[A.cols[A.rpts[i]:A.rpts[i + 1]]].sum() for i in range(A.nrows)])
-    assert np.array_equal(flop, want)
-    assert np.array_equal(key, np.minimum(want, B.ncols))
+def test_heap_arm_is_a_valid_config():
+    d = b.default_config()
+    assert d["heap"] == 0
+    assert b.config_ok(dict(d, heap=1))
+    assert not b.config_ok(dict(d, heap=2))
 
 
 def test_prior_prefers_emptier_tables_for_probing_but_charges_table_size():
