@@ -67,7 +67,7 @@ def input_rows_sorted(srt: bool, input_order: str) -> bool:
     return srt if input_order == "auto" else input_order == "sorted"
 
 
-def make_inputs(name: str, seed: int, sorted_flag, input_order: str = "auto"):
+def make_inputs(name: str, seed: int, sorted_flag, input_order: str = "auto", degree_order: bool = False):
     from synth import (bfs_frontier, erdos_renyi_fixed_degree, rmat, shuffle_within_rows,
                        symmetric_rmat_graph, triangle_inputs, with_values)
     w = WORKLOADS[name]
@@ -87,7 +87,7 @@ def make_inputs(name: str, seed: int, sorted_flag, input_order: str = "auto"):
         return dict(A=A, B=A, sorted=srt)
     if name in ("tri18", "tri18f"):
         g = symmetric_rmat_graph(18, 16, seed)
-        A, L, U = triangle_inputs(g, degree_order=False)
+        A, L, U = triangle_inputs(g, degree_order=degree_order)
         return dict(A=L, B=U, M=A, sorted=True)
     if name == "bfs18":
         A = with_values(rmat(18, 16, seed, values=""), 0, "ones")
@@ -108,6 +108,12 @@ def main():
                     help="column order inside the input rows (rmat20, er20, rmat16); auto: sorted "
                          "for sorted output, shuffled for unsorted output")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--heap", action="store_true",
+                    help="plan with the Heap accumulator for the rows in its envelope (sorted output only)")
+    ap.add_argument("--degree-order", action="store_true",
+                    help="tri18: relabel the graph by ascending degree (Section 5.6) before splitting L and U")
+    ap.add_argument("--no-small-stratum", action="store_true",
+                    help="skip the small-stratum comparison in the headline line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target oracle time of the CPU baseline's row sample")
@@ -123,9 +129,10 @@ def main():
         sys.exit(2)
 
     host_serve = None
-    if args.workload in ("serve", "batch"):
+    headline_small = args.workload == "rmat20" and not args.no_small_stratum
+    if args.workload in ("serve", "batch") or headline_small:
         # operands are generated on a host process pool before anything touches the GPU
-        host_serve = _generate_serve(args, small_only=args.workload == "batch")
+        host_serve = _generate_serve(args, small_only=args.workload != "serve")
 
     import torch
     import paper_1804_01698_amd as sp
@@ -145,7 +152,7 @@ def main():
         return bench_stanza(args, sp, dev)
 
     t_gen = time.perf_counter()
-    inp = make_inputs(args.workload, args.seed, args.sorted_flag, args.input_order)
+    inp = make_inputs(args.workload, args.seed, args.sorted_flag, args.input_order, args.degree_order)
     if args.workload == "tri18f":
         return bench_tri_fused(args, sp, dev, inp)
     log(f"inputs {args.workload}: generated in {time.perf_counter() - t_gen:.1f}s; "
@@ -170,8 +177,10 @@ def main():
     copy_gbs = 5 * 2 * nbytes / (time.perf_counter() - t0) / 1e9
     del src, dst
 
+    cfg = dict(sp.default_config(), heap=1) if args.heap else None
+
     def step(timing: bool):
-        p = sp.Plan([dA], [dB], sorted_output=srt, timing=timing)
+        p = sp.Plan([dA], [dB], sorted_output=srt, timing=timing, config=cfg)
         p.symbolic()
         C = p.numeric()[0]
         p.C = []                      # the plan keeps no reference to C
@@ -278,7 +287,20 @@ def main():
     }
     if dM is not None:
         out["triangles"] = int(extra) // 2
+    if args.heap:
+        out["config"]["accumulator"] = "heap for rows in its envelope (heap_rows = %d)" % st["heap_rows"]
+    if args.degree_order:
+        out["config"]["vertex_order"] = "ascending degree"
 
+    if host_serve is not None:
+        # the served half of the metric: the small stratum through one launch
+        # sequence per product, one batch and the server (inputs of the
+        # headline product freed first)
+        del dA, dB, dM
+        torch.cuda.empty_cache()
+        t_small = time.perf_counter()
+        out["small_stratum"] = measure_small(args, sp, dev, host_serve[1])
+        log(f"small stratum measured in {time.perf_counter() - t_small:.1f}s: {out['small_stratum']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inp, args.cpu_seconds, srt, args.seed)
     print(json.dumps(out), flush=True)
@@ -386,14 +408,20 @@ def _gen_request(r):
     return r, a, b
 
 
+SMALL_FLOP = 2 ** 20       # the small stratum: products of at most this many multiplications
+
+
 def _generate_serve(args, small_only: bool = False):
-    """Requests of the served stream and of its small stratum, with their
-    operands generated on a host process pool (16 workers at most)."""
+    """Requests of the served stream and candidates for its small stratum, with
+    their operands generated on a host process pool (16 workers at most).  The
+    candidates are the stream generator's requests with n*d^2 <= 2^20 (a cheap
+    pre-filter; R-MAT products often exceed it), four per stratum slot: the
+    stratum itself is picked on the device by real flop (small_stratum)."""
     import multiprocessing as mp
     from synth import serving_stream
     t = time.perf_counter()
     reqs = [] if small_only else serving_stream(args.requests, args.seed)
-    small = serving_stream(args.small_requests, args.seed + 1000, max_flop=2 ** 20)
+    small = serving_stream(4 * args.small_requests, args.seed + 1000, max_flop=SMALL_FLOP)
     workers = max(1, min(16, os.cpu_count() or 1))
     # close() + join() rather than the with-block's terminate(): the workers
     # exit on their own instead of being sent SIGTERM
@@ -586,13 +614,91 @@ def bench_tri_fused(args, sp, dev, inp):
     print(json.dumps(out), flush=True)
 
 
+def select_small(sp, dev, small_ops, count):
+    """The small stratum: the first ``count`` candidate requests (stream order)
+    whose product has at most SMALL_FLOP multiplications, counted on the
+    device by the batched path's analysis (the row flop of Fig. 4)."""
+    import torch
+    cand = _upload(sp, small_ops, dev)
+    an = sp.Batch([r.A for r in cand], [r.B for r in cand], [r.sorted_out for r in cand], allocate=False)
+    flops = list(an.flop)
+    del an
+    torch.cuda.synchronize()
+    sel = [r for r, f in zip(cand, flops) if f <= SMALL_FLOP][:count]
+    fsel = [f for f in flops if f <= SMALL_FLOP][:count]
+    return sel, fsel, len(cand)
+
+
+def measure_small(args, sp, dev, small_ops):
+    """The small stratum through (a) one launch sequence per product (plan,
+    symbolic with its sync, allocation, numeric, sync, free: serial), (b) one
+    batch as a caller runs it (upload of the batch description, analysis with
+    its sync, arena, run, sync, result views) and (c) the server with every
+    request queued at t = 0 (its batch worker does (b) plus admission and
+    completion records).  Results of (b) are checked against (a) product by
+    product.  Best of three rounds each."""
+    import torch
+    from paper_1804_01698_amd.serve import Server, serial_products
+    budget = int(args.budget_gb * 1e9)
+    reqs, flops, ncand = select_small(sp, dev, small_ops, args.small_requests)
+    if not reqs:
+        return None
+    Server(budget).run(reqs[:16], realtime=False)
+    serial_products(reqs[:16])
+
+    def batched_direct():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bt = sp.Batch([r.A for r in reqs], [r.B for r in reqs], [r.sorted_out for r in reqs])
+        bt.run()
+        outs = bt.outputs()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, bt, outs
+
+    batched_direct()
+    best = {}
+    rb = None
+    for _ in range(3):
+        tb, bt, outs = batched_direct()
+        r = Server(budget).run(reqs, realtime=False)
+        tsv = max(c.done_s for c in r.completions)
+        ts = serial_products(reqs)
+        for k, v in (("batched", tb), ("server", tsv), ("serial", ts)):
+            best[k] = min(best.get(k, v), v)
+        if rb is None or tsv <= best["server"]:
+            rb = r
+    # results of the batch against the per-product path
+    mism = 0
+    for q, C in zip(reqs, outs):
+        p = sp.Plan([q.A], [q.B], sorted_output=q.sorted_out)
+        p.symbolic()
+        R = p.numeric()[0]
+        torch.cuda.synchronize()
+        p.close()
+        if C is None or C.nnz != R.nnz or not torch.equal(C.rpts, R.rpts):
+            mism += 1
+    sm = rb.summary()
+    n = len(reqs)
+    return {"products": n, "candidates": ncand, "flop_max": SMALL_FLOP, "flop_total": int(sum(flops)),
+            "serial_products_per_s": round(n / best["serial"], 1),
+            "batched_products_per_s": round(n / best["batched"], 1),
+            "server_products_per_s": round(n / best["server"], 1),
+            "speedup_batched": round(best["serial"] / best["batched"], 2),
+            "speedup_server": round(best["serial"] / best["server"], 2),
+            "server_p50_ms": round(sm["p50_ms"], 3), "server_p99_ms": round(sm["p99_ms"], 3),
+            "server_batched": sm["batched"], "server_planned": sm["planned"],
+            "row_count_mismatches": mism,
+            "selection": f"first {n} of {ncand} seeded stream requests with n*d^2 <= 2^20 whose product has "
+                         f"<= 2^20 multiplications (counted by the batch analysis on the device)"}
+
+
 def bench_batch(args, sp, dev, small_ops):
     """The small stratum as one batch: analyse once, then K timed runs of the
     batch (kernels only, products outside the batched range go through the
     plan path on a second stream), against one launch sequence per product."""
     import torch
     from paper_1804_01698_amd.serve import serial_products
-    reqs = _upload(sp, small_ops, dev)
+    reqs, _, ncand = select_small(sp, dev, small_ops, args.small_requests)
     As, Bs, fl = [r.A for r in reqs], [r.B for r in reqs], [r.sorted_out for r in reqs]
     bt = sp.Batch(As, Bs, fl)                      # first construction warms the allocator
     del bt
@@ -684,41 +790,7 @@ def bench_serve(args, sp, dev, main_ops, small_ops):
         log(f"serve at {frac} mu: {loads[f'{frac}mu']}")
     del dreqs
 
-    small = [r for r, _, _ in small_ops]
-    dsmall = _upload(sp, small_ops, dev)
-    Server(budget).run(dsmall[:16], realtime=False)
-    serial_products(dsmall[:16])
-    # the batched path as a caller uses it: upload the batch description, analyse,
-    # run, synchronise; products with a row outside the batched range go through
-    # the plan path one at a time
-    def batched_direct():
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        bt = sp.Batch([r.A for r in dsmall], [r.B for r in dsmall], [r.sorted_out for r in dsmall])
-        bt.run()
-        outs = bt.outputs()
-        rest = [r for r, c in zip(dsmall, outs) if c is None]
-        serial_products(rest)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t, bt, len(rest)
-
-    batched_direct()
-    best = {}
-    for _ in range(3):
-        tb, bt, nrest = batched_direct()
-        rb = Server(budget).run(dsmall, realtime=False)
-        tsv = max(c.done_s for c in rb.completions)
-        ts = serial_products(dsmall)
-        for k, v in (("batched", tb), ("server", tsv), ("serial", ts)):
-            best[k] = min(best.get(k, v), v)
-    # the run alone (kernels only; what a captured graph replays)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(10):
-        bt.run()
-    torch.cuda.synchronize()
-    t_run = (time.perf_counter() - t) / 10
-    sm = rb.summary()
+    small_stratum = measure_small(args, sp, dev, small_ops)
     out = {
         "metric": METRIC,
         "value": round(mu, 2),
@@ -736,13 +808,7 @@ def bench_serve(args, sp, dev, main_ops, small_ops):
                    "budget_gb": args.budget_gb, "operand_gb": round(operand_bytes / 1e9, 3)},
         "saturation": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in ssum.items()},
         "load": loads,
-        "small_stratum": {"requests": len(small), "outside_batched_range": nrest,
-                          "batched_s": round(best["batched"], 5), "serial_s": round(best["serial"], 5),
-                          "speedup": round(best["serial"] / best["batched"], 2),
-                          "batch_run_only_s": round(t_run, 5),
-                          "server_s": round(best["server"], 5),
-                          "server_speedup": round(best["serial"] / best["server"], 2),
-                          "server_batched": sm["batched"], "server_planned": sm["planned"]},
+        "small_stratum": small_stratum,
     }
     print(json.dumps(out), flush=True)
 
