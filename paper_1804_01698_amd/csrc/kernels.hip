@@ -958,8 +958,11 @@ __device__ __forceinline__ void win_issue(WsHdr *wh, unsigned g0, unsigned d, un
     if (d < 8) raw = atomicAdd(&wh->win_next[(g0 + d) % 8], 1u);
 }
 
-// Words of a window's bitmap held in registers ahead of its turn.
-constexpr int WIN_PRE_WORDS = 3;
+// Quads (16-byte groups of four bitmap words) of the next window that each
+// thread holds in registers while the current window's output leaves: thread
+// t takes the contiguous quads [t*S4, t*S4 + S4) of the window, S4 =
+// ceil(nwords / (4*G)), which covers the largest window RANK_BUDGET allows.
+constexpr int WIN_PRE_QUADS = (RANK_BUDGET + 4 * WIN_G - 1) / (4 * WIN_G);
 
 // Numeric phase of the heavy rows, one column window at a time by a
 // persistent grid (one block per CU slot).  A window's output columns are
@@ -972,12 +975,19 @@ constexpr int WIN_PRE_WORDS = 3;
 // spread over the products instead of over words whose bit counts vary from
 // 0 to 32 within a wave.  The slice of B row k inside the window is two loads
 // from k's chunk index, or the whole row (filtered by column) when the row is
-// short.  When the symbolic phase kept the row's bits, pass 1 is a copy of the
-// window's words instead.  For a row of at most 1024 entries of A each
-// thread holds one a_ik and its slice; the next window's item, a_ik and slice
-// are loaded in stages between the current window's passes, so that their
-// latency hides behind loads the window waits for anyway.  Output stores are
-// left in flight (a block barrier does not wait for stores).
+// short.
+// When the symbolic phase kept the rows' bits, a window's words are loaded
+// into registers (contiguous quads per thread) while the previous window's
+// output is being stored, when the registers of the products are free; the
+// window then starts with one pass that counts each thread's bits, scans the
+// counts across the block and writes every word with its rank prefix to LDS.
+// Without stored bits (SPGEMM_LOW_MEMORY) a first pass over the products
+// marks them.  For a row of at most G entries of A each thread holds one a_ik
+// and its slice; the next window's item and a_ik are loaded before the
+// current window's products, its B row pointers and bits before the current
+// output stores and its slice after them, so every level of that chain hides
+// behind work the block does anyway.  Output stores are left in flight (a
+// block barrier does not wait for stores).
 template <typename V>
 __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict__ items, unsigned nitems,
                                                      const int32_t *__restrict__ cA,
@@ -990,6 +1000,7 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
                                                      int32_t *__restrict__ cC, V *__restrict__ vC,
                                                      const uint32_t *__restrict__ bmap, WsHdr *wh) {
     constexpr int G = WIN_G;
+    constexpr int QPC = WORDS_PER_CHUNK / 4;                       // quads per chunk
     __shared__ __align__(16) unsigned long long buf[RANK_BUDGET];   // words, then values
     __shared__ SegLds<G, true, V> sg;
     __shared__ unsigned s_claim[2];
@@ -1011,6 +1022,19 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
             hi = r1;
         }
     };
+    // this thread's quads of window w's stored bits (zero past the window)
+    auto load_bits = [&](const WinItem &w, u32x4 (&q)[WIN_PRE_QUADS]) {
+        const int nq = (w.ch_hi - w.ch_lo) * QPC;
+        const int s4 = (nq + G - 1) / G;
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(bmap + ((size_t)w.slot * nchunks + w.ch_lo) *
+                                                                      WORDS_PER_CHUNK);
+#pragma unroll
+        for (int k = 0; k < WIN_PRE_QUADS; ++k) {
+            const int qi = tid * s4 + k;
+            q[k] = u32x4{0u, 0u, 0u, 0u};
+            if (k < s4 && qi < nq) q[k] = __builtin_nontemporal_load(&src[qi]);
+        }
+    };
 
     if (tid == 0) {
         win_issue(wh, g0, gd, raw);
@@ -1019,8 +1043,7 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
     }
     __syncthreads();
     unsigned cur = __builtin_amdgcn_readfirstlane(s_claim[0]);
-    uint32_t pre[WIN_PRE_WORDS];         // the current window's bitmap words, when preloaded
-    bool have_pre = false;
+    u32x4 q[WIN_PRE_QUADS];              // the current window's bits (stored-bits mode)
     int par = 0;
     WinItem it{};
     int lo = 0, hi = 0;
@@ -1032,6 +1055,7 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
             a = vA[it.a0 + tid];
             slice_of(rB[k], rB[k + 1], long_id[k], it.ch_lo, it.ch_hi, lo, hi);
         }
+        if (bmap) load_bits(it, q);
     }
     while (cur != WIN_NONE) {
         if (tid == 0) {
@@ -1046,66 +1070,57 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
         uint32_t *w32 = reinterpret_cast<uint32_t *>(buf);   // word w: bits w32[2w], rank prefix w32[2w+1]
         V *vals = reinterpret_cast<V *>(buf + nwords);
         int32_t *stage = reinterpret_cast<int32_t *>(buf + nwords + count);   // columns by rank
-        if (bmap && have_pre) {
-#pragma unroll
-            for (int k = 0; k < WIN_PRE_WORDS; ++k)
-                if (tid + k * G < nwords) buf[tid + k * G] = (unsigned long long)pre[k];
-        } else if (bmap) {
-            // the window's occupancy bits from the symbolic phase
-            const uint32_t *src = bmap + ((size_t)it.slot * nchunks + ch_lo) * WORDS_PER_CHUNK;
-            for (int i = tid; i < nwords; i += G) buf[i] = (unsigned long long)__builtin_nontemporal_load(&src[i]);
-        } else {
-            for (int i = tid; i < nwords; i += G) buf[i] = 0ull;
-        }
-        for (int i = tid; i < count; i += G) vals[i] = V(0);
-        __syncthreads();
-
-        // next window, stage 1: its item and this thread's a_ik
-        const unsigned nxt = __builtin_amdgcn_readfirstlane(s_claim[par ^ 1]);
-        WinItem nit{};
-        int nk = -1;
-        V na = V(0);
-        if (nxt != WIN_NONE) {
-            nit = items[nxt];
-            if (nit.a1 - nit.a0 <= G && nit.a0 + tid < nit.a1) {
-                nk = cA[nit.a0 + tid];
-                na = vA[nit.a0 + tid];
-            }
-        }
 
         auto slice = [&](int k, int &l, int &h) {
             slice_of(rB[k], rB[k + 1], long_id[k], it.ch_lo, it.ch_hi, l, h);
         };
-        // pass 1: occupancy bits
-        auto mark = [&](const int (&q)[U_RANK1], const bool (&ok)[U_RANK1], const V (&)[U_RANK1]) {
-            int col[U_RANK1];
+        if (bmap) {
+            // ranks: this thread's bit count, its exclusive prefix over the
+            // block, then each word with its prefix (two words per 16 bytes)
+            const int nq = nwords / 4;
+            const int s4 = (nq + G - 1) / G;
+            int c = 0;
 #pragma unroll
-            for (int u = 0; u < U_RANK1; ++u) {
-                const int c = bc[q[u]];                   // q is always a valid index
-                col[u] = ok[u] ? c : c0 - 1;
-            }
+            for (int k = 0; k < WIN_PRE_QUADS; ++k)
+                c += __popc(q[k].x) + __popc(q[k].y) + __popc(q[k].z) + __popc(q[k].w);
+            int total;
+            int pre = block_excl_scan<G, int>(c, total, sg.wsum);
+            u32x4 *b4 = reinterpret_cast<u32x4 *>(buf);
 #pragma unroll
-            for (int u = 0; u < U_RANK1; ++u) {
-                const uint32_t off = (uint32_t)(col[u] - c0);
-                if (off < span) atomicOr(&w32[2 * (off >> 5)], 1u << (off & 31));
+            for (int k = 0; k < WIN_PRE_QUADS; ++k) {
+                const int qi = tid * s4 + k;
+                if (k < s4 && qi < nq) {
+                    const uint32_t p0 = (uint32_t)pre, p1 = p0 + __popc(q[k].x), p2 = p1 + __popc(q[k].y),
+                                   p3 = p2 + __popc(q[k].z);
+                    b4[2 * qi] = u32x4{q[k].x, p0, q[k].y, p1};
+                    b4[2 * qi + 1] = u32x4{q[k].z, p2, q[k].w, p3};
+                    pre = (int)(p3 + __popc(q[k].w));
+                }
             }
-        };
-        if (!bmap) {
+            if (total != count) bad = true;
+            for (int i = tid; i < count; i += G) vals[i] = V(0);
+        } else {
+            for (int i = tid; i < nwords; i += G) buf[i] = 0ull;
+            for (int i = tid; i < count; i += G) vals[i] = V(0);
+            __syncthreads();
+            // pass 1: occupancy bits from the products
+            auto mark = [&](const int (&qq)[U_RANK1], const bool (&ok)[U_RANK1], const V (&)[U_RANK1]) {
+                int col[U_RANK1];
+#pragma unroll
+                for (int u = 0; u < U_RANK1; ++u) {
+                    const int cb = bc[qq[u]];                 // qq is always a valid index
+                    col[u] = ok[u] ? cb : c0 - 1;
+                }
+#pragma unroll
+                for (int u = 0; u < U_RANK1; ++u) {
+                    const uint32_t off = (uint32_t)(col[u] - c0);
+                    if (off < span) atomicOr(&w32[2 * (off >> 5)], 1u << (off & 31));
+                }
+            };
             if (resident) enum_chunk<G, U_RANK1, false, V>(lo, hi - lo, V(0), sg, mark);
             else enum_row<G, U_RANK1, false, V>(it.a0, it.a1, cA, nullptr, sg, slice, mark);
-        }
-        __syncthreads();
-
-        // next window, stage 2: row pointers of B row k
-        int nr0 = 0, nr1 = 0, nli = -1;
-        if (nk >= 0) {
-            nr0 = rB[nk];
-            nr1 = rB[nk + 1];
-            nli = long_id[nk];
-        }
-
-        // ranks: exclusive prefix of the bit counts, per word
-        {
+            __syncthreads();
+            // ranks: exclusive prefix of the bit counts, per word
             const int S = (nwords + G - 1) / G;
             const int w0 = tid * S;
             int c = 0;
@@ -1122,31 +1137,28 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
         }
         __syncthreads();
 
-        // next window, stage 3: the slice of B row k inside the next window, and
-        // its bitmap words when they fit the registers
-        int nlo = 0, nhi = 0;
-        if (nk >= 0) slice_of(nr0, nr1, nli, nit.ch_lo, nit.ch_hi, nlo, nhi);
-        const int nnw = (nit.ch_hi - nit.ch_lo) * WORDS_PER_CHUNK;
-        const bool npre = bmap && nxt != WIN_NONE && nnw <= WIN_PRE_WORDS * G;
-        uint32_t npw[WIN_PRE_WORDS];
-#pragma unroll
-        for (int k = 0; k < WIN_PRE_WORDS; ++k) npw[k] = 0u;
-        if (npre) {
-            const uint32_t *src = bmap + ((size_t)nit.slot * nchunks + nit.ch_lo) * WORDS_PER_CHUNK;
-#pragma unroll
-            for (int k = 0; k < WIN_PRE_WORDS; ++k)
-                if (tid + k * G < nnw) npw[k] = __builtin_nontemporal_load(&src[tid + k * G]);
+        // next window, stage 1: its item and this thread's a_ik
+        const unsigned nxt = __builtin_amdgcn_readfirstlane(s_claim[par ^ 1]);
+        WinItem nit{};
+        int nk = -1;
+        V na = V(0);
+        if (nxt != WIN_NONE) {
+            nit = items[nxt];
+            if (nit.a1 - nit.a0 <= G && nit.a0 + tid < nit.a1) {
+                nk = cA[nit.a0 + tid];
+                na = vA[nit.a0 + tid];
+            }
         }
 
-        // pass 2: values added at their rank
-        auto add = [&](const int (&q)[U_RANK2], const bool (&ok)[U_RANK2], const V (&av)[U_RANK2]) {
+        // products: values added at their rank
+        auto add = [&](const int (&qq)[U_RANK2], const bool (&ok)[U_RANK2], const V (&av)[U_RANK2]) {
             int col[U_RANK2];
             V x[U_RANK2];
 #pragma unroll
             for (int u = 0; u < U_RANK2; ++u) {
-                const int c = bc[q[u]];                   // q is always a valid index
-                const V b = bv[q[u]];
-                col[u] = ok[u] ? c : c0 - 1;
+                const int cb = bc[qq[u]];                     // qq is always a valid index
+                const V b = bv[qq[u]];
+                col[u] = ok[u] ? cb : c0 - 1;
                 x[u] = ok[u] ? av[u] * b : V(0);
             }
 #pragma unroll
@@ -1166,11 +1178,28 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
         else enum_row<G, U_RANK2, true, V>(it.a0, it.a1, cA, vA, sg, slice, add);
         __syncthreads();
 
+        // next window, stage 2: row pointers of B row k, and the window's bits
+        int nr0 = 0, nr1 = 0, nli = -1;
+        if (nk >= 0) {
+            nr0 = rB[nk];
+            nr1 = rB[nk + 1];
+            nli = long_id[nk];
+        }
+        // (every path sets q here: the previous window's bits are dead
+        // through the products, so their registers are free there)
+#pragma unroll
+        for (int k = 0; k < WIN_PRE_QUADS; ++k) q[k] = u32x4{0u, 0u, 0u, 0u};
+        if (bmap && nxt != WIN_NONE) load_bits(nit, q);
+
         // values and columns leave in consecutive runs
         for (int r = tid; r < count; r += G) {
             __builtin_nontemporal_store(stage[r], &cC[it.out_pos + r]);
             __builtin_nontemporal_store(vals[r], &vC[it.out_pos + r]);
         }
+
+        // next window, stage 3: the slice of B row k inside the next window
+        int nlo = 0, nhi = 0;
+        if (nk >= 0) slice_of(nr0, nr1, nli, nit.ch_lo, nit.ch_hi, nlo, nhi);
         __syncthreads();
 
         cur = nxt;
@@ -1178,9 +1207,6 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
         lo = nlo;
         hi = nhi;
         a = na;
-#pragma unroll
-        for (int k = 0; k < WIN_PRE_WORDS; ++k) pre[k] = npw[k];
-        have_pre = npre;
         par ^= 1;
     }
     if (bad) atomicOr(&wh->err, ERR_COUNT);
