@@ -218,21 +218,14 @@ struct SegLds {
 // multiplier a (numeric phase), ok = valid.  q is a valid B index even where
 // ok is false (the first entry of some segment), so act may load at q
 // unconditionally and discard the value.
+// The batches of products of segments already laid out in sg (nseg
+// segments, total products; see enum_chunk), ending with a block barrier.
 template <int G, int U, bool NUM, typename V, bool SNUM, class ActF>
-__device__ __forceinline__ void enum_chunk(int lo, int len, V a, SegLds<G, SNUM, V> &sg, ActF act) {
+__device__ __forceinline__ void enum_walk(int total, int nseg, SegLds<G, SNUM, V> &sg, ActF act) {
     static_assert(SNUM || !NUM, "numeric enumeration needs room for the multipliers");
     constexpr int NW = G / WAVE;
     const int ln = threadIdx.x & 63;
     const int w = G == WAVE ? 0 : (int)(threadIdx.x >> 6);   // G == 64: one wave of a larger block
-    int total, nseg;
-    const int pre_len = block_excl_scan<G, int>(len, total, sg.wsum);
-    const int pre_ne = block_excl_scan<G, int>(len > 0 ? 1 : 0, nseg, sg.wsum);
-    if (len > 0) {
-        sg.lo[pre_ne] = lo;
-        sg.off[pre_ne] = pre_len;
-        if constexpr (NUM) sg.a[pre_ne] = a;
-    }
-    block_sync<G>();
     const int P0 = (int)(((long long)w * total) / NW);
     const int P1 = (int)(((long long)(w + 1) * total) / NW);
     if (P0 < P1) {
@@ -310,6 +303,20 @@ __device__ __forceinline__ void enum_chunk(int lo, int len, V a, SegLds<G, SNUM,
         }
     }
     block_sync<G>();
+}
+
+template <int G, int U, bool NUM, typename V, bool SNUM, class ActF>
+__device__ __forceinline__ void enum_chunk(int lo, int len, V a, SegLds<G, SNUM, V> &sg, ActF act) {
+    int total, nseg;
+    const int pre_len = block_excl_scan<G, int>(len, total, sg.wsum);
+    const int pre_ne = block_excl_scan<G, int>(len > 0 ? 1 : 0, nseg, sg.wsum);
+    if (len > 0) {
+        sg.lo[pre_ne] = lo;
+        sg.off[pre_ne] = pre_len;
+        if constexpr (NUM) sg.a[pre_ne] = a;
+    }
+    block_sync<G>();
+    enum_walk<G, U, NUM, V>(total, nseg, sg, act);
 }
 
 // All A entries [a0, a1) of a row, G at a time; slice(k, lo, hi) gives the

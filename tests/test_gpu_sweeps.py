@@ -101,3 +101,18 @@ def test_stanza_read_rejects_bad_arguments(sp):
         sp.stanza_read(base, st, 25)
     with pytest.raises(sp.SpgemmError):
         sp.stanza_read(base, st.to(torch.int32), 0)
+
+
+@pytest.mark.parametrize("nbytes", [16, 16 * 1023, 16 * (4096 * 4 + 7), 16 * ((1 << 22) + 5)])
+def test_stream_copy_is_exact(sp, nbytes):
+    """The copy-rate probe copies every byte (ragged tails of its 4-deep
+    per-lane steps included) and nothing past the count."""
+    import torch
+    _note(f"case stream copy {nbytes} bytes")
+    g = torch.Generator(device="cpu").manual_seed(nbytes)
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, generator=g).to("cuda")
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    sp.stream_copy(dst[:nbytes], src)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src)
+    assert int(dst[nbytes:].sum()) == 0
