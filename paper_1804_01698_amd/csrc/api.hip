@@ -60,7 +60,7 @@ struct Prod {
     size_t ws_base = 0, ws_bytes = 0;
     size_t o_hdr = 0, o_perm_sym = 0, o_perm_num = 0, o_nnz = 0, o_bsum = 0;
     size_t o_chunk = 0, o_heavy = 0, o_items = 0, o_bc = 0, o_bv = 0, o_long = 0;
-    size_t o_whist = 0, o_long_id = 0, o_idx = 0, o_slot = 0, o_bperm = 0, o_bmap = 0, o_bs = 0;
+    size_t o_whist = 0, o_long_id = 0, o_idx = 0, o_slot = 0, o_bperm = 0, o_bmap = 0, o_bs = 0, o_ki = 0;
     bool store_bm = false;    // symbolic bitmaps kept for the numeric windows
     // after symbolic
     char *ws = nullptr;
@@ -351,6 +351,7 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
             q.o_long = o; o += align_up(4 * (size_t)q.B.nrows);
             q.o_long_id = o; o += align_up(4 * (size_t)q.B.nrows);
             q.o_idx = o; o += align_up(4 * (size_t)q.h.n_long_b * (size_t)(q.nchunks + 1));
+            q.o_ki = o; o += align_up(8 * (size_t)q.A.nnz);
         }
         q.ws_bytes = o;
         ws += o;
@@ -394,6 +395,11 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
                                                  q.at<int32_t>(q.o_idx), q.nchunks, q.wh, s);
                         }),
                   "bucket_B");
+            HIPCK(timed(pl, "entry_brow", 20.0 * q.A.nnz,
+                        [&] {
+                            return launch_entry_brow(q.A, q.B, q.at<int32_t>(q.o_long_id), q.at<int2>(q.o_ki), s);
+                        }),
+                  "entry_brow");
         }
         // largest tables first: long-running blocks start early
         for (int b = NSB - 1; b >= 1; --b) {
@@ -544,8 +550,8 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
                                  12.0 * q.hw.num_flop[hb] + 12.0 * q.hw.num_nnzc[hb];
             HIPCK(timed(pl, "num_window", bytes,
                         [&] {
-                            return launch_num_window(pl->dtype, q.hw.n_items, q.at<WinItem>(q.o_items), q.A, q.B,
-                                                     q.at<int32_t>(q.o_long_id), q.at<int32_t>(q.o_idx), q.nchunks,
+                            return launch_num_window(pl->dtype, q.hw.n_items, q.at<WinItem>(q.o_items), q.A,
+                                                     q.at<int2>(q.o_ki), q.at<int32_t>(q.o_idx), q.nchunks,
                                                      q.at<int32_t>(q.o_bc), q.at<void>(q.o_bv), cols_C[p],
                                                      vals_C[p], q.store_bm ? q.at<uint32_t>(q.o_bmap) : nullptr,
                                                      q.wh, pl->ncu, s);

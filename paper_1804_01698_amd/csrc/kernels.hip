@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "config.hpp"
 #include "device.hpp"
 #include "launch.hpp"
@@ -775,6 +777,21 @@ __global__ __launch_bounds__(256) void k_gather_vals(int64_t n, const int32_t *_
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += stride) bv[p] = vB[bperm[p]];
 }
 
+// What the window kernel needs of the B row an entry a_ik selects, per entry
+// of A (so that a window's slices are one load plus the chunk index away from
+// its A range, not three): ki[e] = {start of B row k, its chunk-index id}, or
+// for a row without an index {start, -1 - length}.
+__global__ __launch_bounds__(256) void k_entry_brow(int64_t nnz, const int32_t *__restrict__ cA,
+                                                    const int32_t *__restrict__ rB,
+                                                    const int32_t *__restrict__ long_id, int2 *__restrict__ ki) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nnz; e += stride) {
+        const int k = cA[e];
+        const int r0 = rB[k], li = long_id[k];
+        ki[e] = make_int2(r0, li >= 0 ? li : -1 - (rB[k + 1] - r0));
+    }
+}
+
 // ----------------------------------------------------------------------- numeric
 
 // Column passes of the rank sort of a wide bin before it falls back to bitonic
@@ -990,10 +1007,8 @@ constexpr int WIN_PRE_QUADS = (RANK_BUDGET + 4 * WIN_G - 1) / (4 * WIN_G);
 // block barrier does not wait for stores).
 template <typename V>
 __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict__ items, unsigned nitems,
-                                                     const int32_t *__restrict__ cA,
+                                                     const int2 *__restrict__ ki,
                                                      const V *__restrict__ vA,
-                                                     const int32_t *__restrict__ rB,
-                                                     const int32_t *__restrict__ long_id,
                                                      const int32_t *__restrict__ idx, int nchunks,
                                                      const int32_t *__restrict__ bc,
                                                      const V *__restrict__ bv,
@@ -1013,15 +1028,16 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
     bool bad = false;
     int ptotal = 0, pnseg = 0;           // products and segments laid out at the window's start
 
-    // the slice of B row k inside chunks [ch_lo, ch_hi)
-    auto slice_of = [&](int r0, int r1, int li, int ch_lo, int ch_hi, int &lo, int &hi) {
-        if (li >= 0) {
-            const int32_t *ix = idx + (size_t)li * nch1;
-            lo = r0 + ix[ch_lo];
-            hi = r0 + ix[ch_hi];
+    // the slice inside chunks [ch_lo, ch_hi) of the B row that entry info b
+    // describes (k_entry_brow)
+    auto slice_of = [&](int2 b, int ch_lo, int ch_hi, int &lo, int &hi) {
+        if (b.y >= 0) {
+            const int32_t *ix = idx + (size_t)b.y * nch1;
+            lo = b.x + ix[ch_lo];
+            hi = b.x + ix[ch_hi];
         } else {
-            lo = r0;
-            hi = r1;
+            lo = b.x;
+            hi = b.x - 1 - b.y;
         }
     };
     // this thread's quads of window w's stored bits (zero past the window)
@@ -1053,9 +1069,8 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
     if (cur != WIN_NONE) {
         it = items[cur];
         if (it.a1 - it.a0 <= G && it.a0 + tid < it.a1) {
-            const int k = cA[it.a0 + tid];
             a = vA[it.a0 + tid];
-            slice_of(rB[k], rB[k + 1], long_id[k], it.ch_lo, it.ch_hi, lo, hi);
+            slice_of(ki[it.a0 + tid], it.ch_lo, it.ch_hi, lo, hi);
         }
         if (bmap) load_bits(it, q);
     }
@@ -1073,8 +1088,20 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
         V *vals = reinterpret_cast<V *>(buf + nwords);
         int32_t *stage = reinterpret_cast<int32_t *>(buf + nwords + count);   // columns by rank
 
-        auto slice = [&](int k, int &l, int &h) {
-            slice_of(rB[k], rB[k + 1], long_id[k], it.ch_lo, it.ch_hi, l, h);
+        // a row of more than G entries of A: its slices G entries at a time
+        auto walk_row = [&](auto &&act, auto tag) {
+            constexpr bool NUMW = decltype(tag)::value;
+            for (int cb = it.a0; cb < it.a1; cb += G) {
+                const int e = cb + tid;
+                int l = 0, h = 0;
+                V av = V(0);
+                if (e < it.a1) {
+                    slice_of(ki[e], it.ch_lo, it.ch_hi, l, h);
+                    if constexpr (NUMW) av = vA[e];
+                }
+                if constexpr (NUMW) enum_chunk<G, U_RANK2, true, V>(l, h - l, av, sg, act);
+                else enum_chunk<G, U_RANK1, false, V>(l, h - l, V(0), sg, act);
+            }
         };
         if (bmap) {
             // ranks: this thread's bit count, its exclusive prefix over the
@@ -1141,7 +1168,7 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
                 }
             };
             if (resident) enum_chunk<G, U_RANK1, false, V>(lo, hi - lo, V(0), sg, mark);
-            else enum_row<G, U_RANK1, false, V>(it.a0, it.a1, cA, nullptr, sg, slice, mark);
+            else walk_row(mark, std::false_type{});
             __syncthreads();
             // ranks: exclusive prefix of the bit counts, per word
             const int S = (nwords + G - 1) / G;
@@ -1160,15 +1187,17 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
         }
         __syncthreads();
 
-        // next window, stage 1: its item and this thread's a_ik
+        // next window, stage 1: its item, this thread's a_ik and its B row
         const unsigned nxt = __builtin_amdgcn_readfirstlane(s_claim[par ^ 1]);
         WinItem nit{};
-        int nk = -1;
+        bool nres = false;
+        int2 nb = make_int2(0, -1);
         V na = V(0);
         if (nxt != WIN_NONE) {
             nit = items[nxt];
             if (nit.a1 - nit.a0 <= G && nit.a0 + tid < nit.a1) {
-                nk = cA[nit.a0 + tid];
+                nres = true;
+                nb = ki[nit.a0 + tid];
                 na = vA[nit.a0 + tid];
             }
         }
@@ -1199,16 +1228,12 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
         };
         if (resident && bmap) enum_walk<G, U_RANK2, true, V>(ptotal, pnseg, sg, add);   // laid out above
         else if (resident) enum_chunk<G, U_RANK2, true, V>(lo, hi - lo, a, sg, add);
-        else enum_row<G, U_RANK2, true, V>(it.a0, it.a1, cA, vA, sg, slice, add);
+        else walk_row(add, std::true_type{});
         __syncthreads();
 
-        // next window, stage 2: row pointers of B row k, and the window's bits
-        int nr0 = 0, nr1 = 0, nli = -1;
-        if (nk >= 0) {
-            nr0 = rB[nk];
-            nr1 = rB[nk + 1];
-            nli = long_id[nk];
-        }
+        // next window, stage 2: its slice (the chunk index) and its bits
+        int nlo = 0, nhi = 0;
+        if (nres) slice_of(nb, nit.ch_lo, nit.ch_hi, nlo, nhi);
         // (every path sets q here: the previous window's bits are dead
         // through the products, so their registers are free there)
 #pragma unroll
@@ -1221,9 +1246,6 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
             __builtin_nontemporal_store(vals[r], &vC[it.out_pos + r]);
         }
 
-        // next window, stage 3: the slice of B row k inside the next window
-        int nlo = 0, nhi = 0;
-        if (nk >= 0) slice_of(nr0, nr1, nli, nit.ch_lo, nit.ch_hi, nlo, nhi);
         __syncthreads();
 
         cur = nxt;
@@ -1752,6 +1774,13 @@ hipError_t launch_gather_vals(int dtype, int64_t n, const int32_t *bperm, const 
     return hipGetLastError();
 }
 
+hipError_t launch_entry_brow(const CsrDev &A, const CsrDev &B, const int32_t *long_id, int2 *ki, hipStream_t s) {
+    if (A.nnz == 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<int64_t>(grid1(A.nnz, 256), 256 * 32);
+    k_entry_brow<<<g, 256, 0, s>>>(A.nnz, A.cols, B.rpts, long_id, ki);
+    return hipGetLastError();
+}
+
 hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
                               const BinOffsets &off, int32_t *perm, WsHdr *wh, const BinLimits &L, hipStream_t s) {
     if (m == 0) return hipSuccess;
@@ -1810,24 +1839,22 @@ __global__ void k_zero_u32n(unsigned *p, int n) {
 
 
 // Windows leave in ascending column order, so sorted and unsorted output share it.
-hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
-                             const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
-                             const void *bv, int32_t *cC, void *vC, const uint32_t *bmap, WsHdr *wh, int ncu,
-                             hipStream_t s) {
+hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const int2 *ki,
+                             const int32_t *idx, int nchunks, const int32_t *bc, const void *bv, int32_t *cC,
+                             void *vC, const uint32_t *bmap, WsHdr *wh, int ncu, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
     k_zero_u32n<<<1, 64, 0, s>>>(wh->win_next, 8);
     if (dtype == 0) {
         static const int occ = blocks_per_cu(k_num_window<double>, WIN_G);
         const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
-        k_num_window<double><<<grid, WIN_G, 0, s>>>(items, nitems, A.cols, (const double *)A.vals, B.rpts, long_id,
-                                                   idx, nchunks, bc, (const double *)bv, cC, (double *)vC, bmap,
-                                                   wh);
+        k_num_window<double><<<grid, WIN_G, 0, s>>>(items, nitems, ki, (const double *)A.vals, idx, nchunks, bc,
+                                                    (const double *)bv, cC, (double *)vC, bmap, wh);
     } else {
         static const int occ = blocks_per_cu(k_num_window<unsigned long long>, WIN_G);
         const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);
         k_num_window<unsigned long long><<<grid, WIN_G, 0, s>>>(
-            items, nitems, A.cols, (const unsigned long long *)A.vals, B.rpts, long_id, idx, nchunks, bc,
-            (const unsigned long long *)bv, cC, (unsigned long long *)vC, bmap, wh);
+            items, nitems, ki, (const unsigned long long *)A.vals, idx, nchunks, bc, (const unsigned long long *)bv,
+            cC, (unsigned long long *)vC, bmap, wh);
     }
     return hipGetLastError();
 }

@@ -51,10 +51,10 @@ hipError_t launch_num_heap(int dtype, unsigned nrows, const int32_t *perm, int64
 hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
                           const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
                           WsHdr *wh, HashCfg hc, int ncu, hipStream_t s);
-hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const CsrDev &B,
-                             const int32_t *long_id, const int32_t *idx, int nchunks, const int32_t *bc,
-                             const void *bv, int32_t *cC, void *vC, const uint32_t *bmap, WsHdr *wh, int ncu,
-                             hipStream_t s);
+hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const int2 *ki,
+                             const int32_t *idx, int nchunks, const int32_t *bc, const void *bv, int32_t *cC,
+                             void *vC, const uint32_t *bmap, WsHdr *wh, int ncu, hipStream_t s);
+hipError_t launch_entry_brow(const CsrDev &A, const CsrDev &B, const int32_t *long_id, int2 *ki, hipStream_t s);
 hipError_t launch_masked_product(const CsrDev &A, const CsrDev &B, const CsrDev &M, bool ones, unsigned *next_row,
                                  int64_t *out, int ncu, hipStream_t s);
 hipError_t launch_masked_sum(int64_t m, int64_t ncols, const int64_t *rC, const int32_t *cC, const int64_t *vC,
