@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--heap", action="store_true",
                     help="plan with the Heap accumulator for the rows in its envelope (sorted output only)")
+    ap.add_argument("--bucket-slots", type=int, default=4, choices=(4, 8, 16),
+                    help="slots per bucket of the LDS hash tables (8 and 16: the HashVector-style chunks)")
     ap.add_argument("--degree-order", action="store_true",
                     help="tri18: relabel the graph by ascending degree (Section 5.6) before splitting L and U")
     ap.add_argument("--no-small-stratum", action="store_true",
@@ -177,7 +179,9 @@ def main():
     copy_gbs = 5 * 2 * nbytes / (time.perf_counter() - t0) / 1e9
     del src, dst
 
-    cfg = dict(sp.default_config(), heap=1) if args.heap else None
+    cfg = None
+    if args.heap or args.bucket_slots != 4:
+        cfg = dict(sp.default_config(), heap=1 if args.heap else 0, bucket_slots=args.bucket_slots)
 
     def step(timing: bool):
         p = sp.Plan([dA], [dB], sorted_output=srt, timing=timing, config=cfg)
@@ -289,6 +293,8 @@ def main():
         out["triangles"] = int(extra) // 2
     if args.heap:
         out["config"]["accumulator"] = "heap for rows in its envelope (heap_rows = %d)" % st["heap_rows"]
+    if args.bucket_slots != 4:
+        out["config"]["bucket_slots"] = args.bucket_slots
     if args.degree_order:
         out["config"]["vertex_order"] = "ascending degree"
 
