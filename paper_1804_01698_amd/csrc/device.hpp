@@ -163,6 +163,21 @@ __device__ __forceinline__ int bkt_insert(int *keys, V *vals, uint32_t T, int ke
     const uint32_t bq = FIXED_BQ > 0 ? (uint32_t)FIXED_BQ : bq_rt;
     const uint32_t W = BKT * bq;                   // slots per bucket
     const uint32_t NB = T / W;
+    if (bq == 1) {
+        // 4-slot buckets: the key's own slot (inside its bucket) is tried
+        // first with one CAS, which settles the insert when that slot was
+        // empty or already held the key; otherwise the bucket is scanned.  A
+        // key then sits either in its own slot or in the first slot of the
+        // bucket that was empty when it arrived, both inside the bucket that
+        // every insert of the key reads whole, so no duplicate can arise.
+        const uint32_t h = hash_slot(key, T, mul);
+        if (probes) ++*probes;
+        const int old = atomicCAS(&keys[h], -1, key);
+        if (old == -1 || old == key) {
+            if constexpr (NUM) lds_add(&vals[h], x);
+            return old == -1;
+        }
+    }
     uint32_t b = hash_slot(key, NB, mul);
     uint32_t q = 0;                                // quad of the bucket being read
     for (uint32_t it = 0; it < T / BKT + T; ++it) {
@@ -206,7 +221,7 @@ __device__ __forceinline__ int bkt_insert(int *keys, V *vals, uint32_t T, int ke
 // and one round of U independent global loads per lane.
 template <int G, bool NUM, typename V>
 struct SegLds {
-    int lo[G];
+    int base[G];      // B index of the segment's product 0 minus its offset: product p reads B at base + p
     int off[G];
     V a[NUM ? G : 1];
     int wsum[G / WAVE + 1];
@@ -229,8 +244,9 @@ __device__ __forceinline__ void enum_walk(int total, int nseg, SegLds<G, SNUM, V
     const int P0 = (int)(((long long)w * total) / NW);
     const int P1 = (int)(((long long)(w + 1) * total) / NW);
     if (P0 < P1) {
+        // segment of the wave's first product (segment 0 holds product 0)
         int e = 0;
-        {
+        if (P0 > 0) {
             int hi = nseg - 1;
             while (e < hi) {
                 const int mid = (e + hi + 1) >> 1;
@@ -239,25 +255,35 @@ __device__ __forceinline__ void enum_walk(int total, int nseg, SegLds<G, SNUM, V
         }
         for (int pb = P0; pb < P1; pb += WAVE * U) {
             const int last = min(pb + WAVE * U, P1) - 1;
-            int eh = e, step = 1;
-            while (eh + step < nseg && sg.off[eh + step] <= last) { eh += step; step <<= 1; }
-            int top = min(eh + step, nseg) - 1;
-            while (eh < top) {
-                const int mid = (eh + top + 1) >> 1;
-                if (sg.off[mid] <= last) eh = mid; else top = mid - 1;
+            // segment of the batch's last product: the last segment when the
+            // batch ends the row, else by galloping and bisection from e
+            int eh = e;
+            if (last == total - 1) {
+                eh = nseg - 1;
+            } else {
+                int step = 1;
+                while (eh + step < nseg && sg.off[eh + step] <= last) { eh += step; step <<= 1; }
+                int top = min(eh + step, nseg) - 1;
+                while (eh < top) {
+                    const int mid = (eh + top + 1) >> 1;
+                    if (sg.off[mid] <= last) eh = mid; else top = mid - 1;
+                }
             }
+            // lanes past the range read the batch's last product again (a
+            // valid index) so that loads need no branch
             int q[U];
             bool ok[U];
             V av[U];
             if (e == eh) {
                 // the whole batch lies in one segment: uniform base, no search
-                const int base = sg.lo[e] - sg.off[e] + pb + ln;
+                const int base = sg.base[e];
                 V a1 = V(0);
                 if constexpr (NUM) a1 = sg.a[e];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    ok[u] = pb + WAVE * u + ln <= last;
-                    q[u] = ok[u] ? base + WAVE * u : sg.lo[e];
+                    const int p = pb + WAVE * u + ln;
+                    ok[u] = p <= last;
+                    q[u] = base + min(p, last);
                     av[u] = a1;
                 }
             } else {
@@ -290,9 +316,7 @@ __device__ __forceinline__ void enum_walk(int total, int nseg, SegLds<G, SNUM, V
                     const uint32_t upto = (uint32_t)((2ull << (rel & 31)) - 1ull);
                     const int seg = e + (int)bw.y + __popc(bw.x & upto);
                     ok[u] = p <= last;
-                    // lanes past the range point at their segment's first entry
-                    // (a valid index) so that loads need no branch
-                    q[u] = sg.lo[seg] + (ok[u] ? p - sg.off[seg] : 0);
+                    q[u] = sg.base[seg] + min(p, last);    // p > last: seg is eh, which holds last
                     av[u] = V(0);
                     if constexpr (NUM) av[u] = sg.a[seg];
                 }
@@ -311,7 +335,7 @@ __device__ __forceinline__ void enum_chunk(int lo, int len, V a, SegLds<G, SNUM,
     const int pre_len = block_excl_scan<G, int>(len, total, sg.wsum);
     const int pre_ne = block_excl_scan<G, int>(len > 0 ? 1 : 0, nseg, sg.wsum);
     if (len > 0) {
-        sg.lo[pre_ne] = lo;
+        sg.base[pre_ne] = lo - pre_len;
         sg.off[pre_ne] = pre_len;
         if constexpr (NUM) sg.a[pre_ne] = a;
     }
@@ -412,6 +436,67 @@ __device__ __forceinline__ int compact_store(int *keys, V *vals, int *wsum, int6
         __builtin_nontemporal_store(vals[j], &valsC[out_pos + j]);
     }
     return total;
+}
+
+// Unsorted output of a finished table: wave w takes the slots [w*T/NW,
+// (w+1)*T/NW), read lane by lane (conflict-free), counts its keys from one
+// ballot per row of 64 slots, the counts are scanned across the waves, and
+// each wave writes its entries in the runs the ballots give: the entries go
+// from the table to C with no LDS round trip.  Returns the number of keys.
+template <int G, int T, typename V>
+__device__ __forceinline__ int compact_store_unsorted(const int *keys, const V *vals, int *wsum, int64_t out_pos,
+                                                      int expected, int32_t *__restrict__ colsC,
+                                                      V *__restrict__ valsC, int *err) {
+    constexpr int NW = G / WAVE;
+    static_assert(T % G == 0, "table size a multiple of the block");
+    constexpr int S = T / G;
+    const int ln = lane_id();
+    const int w = NW == 1 ? 0 : (int)(threadIdx.x >> 6);
+    const int *kw = keys + w * (T / NW);
+    int kk[S];
+    unsigned long long m[S];
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        kk[j] = kw[j * WAVE + ln];
+        m[j] = __ballot(kk[j] != -1);
+        c += __popcll(m[j]);
+    }
+    int base = 0, total = c;
+    if constexpr (NW > 1) {
+        if (ln == 0) wsum[w] = c;
+        __syncthreads();
+        const int v = ln < NW ? wsum[ln] : 0;
+        base = wave_sum_i32(ln < w ? v : 0);
+        total = wave_sum_i32(v);
+        __syncthreads();                      // wsum is free again
+    }
+    const V *vw = vals + w * (T / NW);
+    const unsigned long long below = (1ull << ln) - 1ull;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int pos = base + __popcll(m[j] & below);
+        if (kk[j] != -1 && pos < expected) {
+            __builtin_nontemporal_store(kk[j], &colsC[out_pos + pos]);
+            __builtin_nontemporal_store(vw[j * WAVE + ln], &valsC[out_pos + pos]);
+        }
+        base += __popcll(m[j]);
+    }
+    if (total != expected && threadIdx.x == 0) atomicOr(err, ERR_COUNT);
+    return total;
+}
+
+// Empty a table of T keys (and with NUM its 8-byte values, zeroed): 16-byte
+// LDS stores; both arrays 16-byte aligned.
+template <int G, int T, bool NUM, typename V>
+__device__ __forceinline__ void table_clear(int *keys, V *vals) {
+    static_assert(T % 4 == 0 && sizeof(V) == 8, "table layout");
+    int4 *k4 = reinterpret_cast<int4 *>(keys);
+    for (int i = (int)threadIdx.x; i < T / 4; i += G) k4[i] = make_int4(-1, -1, -1, -1);
+    if constexpr (NUM) {
+        ulonglong2 *v2 = reinterpret_cast<ulonglong2 *>(vals);
+        for (int i = (int)threadIdx.x; i < T / 2; i += G) v2[i] = make_ulonglong2(0ull, 0ull);
+    }
 }
 
 }  // namespace spg

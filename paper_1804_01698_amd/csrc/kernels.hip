@@ -285,7 +285,7 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
     else cur = RowPre<double>{perm[perm_off + it], 0, 0, -1, 0, 0, 0.0};
     while (true) {
         const int row = cur.row;
-        for (int i = tid; i < T; i += G) tab[i] = -1;
+        table_clear<G, T, false, double>(tab, nullptr);
         __syncthreads();
         const unsigned nit = it + step;
         RowPre<double> nxt{};
@@ -821,7 +821,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
                                                 int32_t *__restrict__ cC, V *__restrict__ vC,
                                                 WsHdr *wh, HashCfg hc, int64_t ncolsB) {
     __shared__ __align__(16) int keys[T];
-    __shared__ V vals[T];
+    __shared__ __align__(16) V vals[T];
     __shared__ __align__(16) NumLds<G, V> lds;
     __shared__ int rank_ws[G / WAVE + 1];
     SegLds<G, true, V> &sg = lds.sg;
@@ -835,7 +835,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
     else cur = RowPre<V>{perm[perm_off + it], 0, 0, -1, 0, 0, V(0)};
     while (true) {
         const int row = cur.row;
-        for (int i = tid; i < T; i += G) { keys[i] = -1; vals[i] = V(0); }
+        table_clear<G, T, true, V>(keys, vals);
         __syncthreads();
         // the next row's A entries are loaded while this row's products run
         const unsigned nit = it + step;
@@ -940,7 +940,8 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
                 ranked = true;
             }
         }
-        if (!ranked) compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
+        if constexpr (!SORTED) compact_store_unsorted<G, T, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
+        else if (!ranked) compact_store<G, T, SORTED, V>(keys, vals, sg.wsum, o, expected, cC, vC, &wh->err);
         if (!PERSIST || nit >= nrows) break;
         __syncthreads();                                      // the table is reused by the next row
         it = nit;
@@ -1128,8 +1129,9 @@ __global__ __launch_bounds__(WIN_G) void k_num_window(const WinItem *__restrict_
             if (resident) {
                 const int pre_ne = (int)(pex & 2047u);
                 if (len > 0) {
-                    sg.lo[pre_ne] = lo;
-                    sg.off[pre_ne] = (int)((pex >> 11) & 0x7FFFFFFFull);
+                    const int po = (int)((pex >> 11) & 0x7FFFFFFFull);
+                    sg.base[pre_ne] = lo - po;
+                    sg.off[pre_ne] = po;
                     sg.a[pre_ne] = a;
                 }
                 ptotal = __builtin_amdgcn_readfirstlane((int)((ptot >> 11) & 0x7FFFFFFFull));
