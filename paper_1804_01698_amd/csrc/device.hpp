@@ -18,26 +18,62 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Value of x from another lane by a DPP move (VALU only, no LDS): lanes
+// whose source lies outside the pattern, or whose row is outside ROW_MASK,
+// get 0.  CTRL 0x110+n = shift right by n within each row of 16 lanes;
+// 0x142 = lane 15 of each row to the whole next row; 0x143 = lane 31 to the
+// rows above it.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i32(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp_move(T x) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, dpp_i32<CTRL, ROW_MASK>(__builtin_bit_cast(int, x)));
+    } else {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+        const unsigned lo = (unsigned)dpp_i32<CTRL, ROW_MASK>((int)(unsigned)u);
+        const unsigned hi = (unsigned)dpp_i32<CTRL, ROW_MASK>((int)(unsigned)(u >> 32));
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    }
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active):
+// Hillis-Steele steps of 1, 2, 4, 8 inside each row of 16 lanes, then the
+// row totals are carried upward by two broadcasts.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T x) {
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const T y = __shfl_up(x, d);
-        if (lane_id() >= d) x += y;
-    }
+    x += dpp_move<0x111, 0xF>(x);
+    x += dpp_move<0x112, 0xF>(x);
+    x += dpp_move<0x114, 0xF>(x);
+    x += dpp_move<0x118, 0xF>(x);
+    x += dpp_move<0x142, 0xA>(x);
+    x += dpp_move<0x143, 0xC>(x);
     return x;
+}
+
+// Value of lane 63 (uniform).
+template <typename T>
+__device__ __forceinline__ T wave_last(T x) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+    } else {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    }
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d);
-    return x;
+    return wave_last(wave_incl_scan(x));
 }
 
 __device__ __forceinline__ int wave_sum_i32(int x) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d);
-    return x;
+    return wave_last(wave_incl_scan(x));
 }
 
 // Exclusive scan over a block of G threads (G a multiple of 64, <= 1024).
@@ -47,7 +83,7 @@ __device__ __forceinline__ T block_excl_scan(T x, T &total, T *wsum) {
     constexpr int NW = G / WAVE;
     const T incl = wave_incl_scan<T>(x);
     if constexpr (NW == 1) {
-        total = __shfl(incl, 63);
+        total = wave_last(incl);
         return incl - x;
     } else {
         const int w = threadIdx.x >> 6;
@@ -129,18 +165,17 @@ __device__ __forceinline__ int4 lds_load4(const int *p) {
 // Slot of key in the bucket (match or first empty), -1 if full without it;
 // empty_hit says the slot is empty (needs a CAS).
 __device__ __forceinline__ int bucket_pick(int4 k, int key, bool &empty_hit) {
-    empty_hit = false;
-    if (k.x == key) return 0;
-    if (k.y == key) return 1;
-    if (k.z == key) return 2;
-    if (k.w == key) return 3;
-    empty_hit = true;
-    if (k.x == -1) return 0;
-    if (k.y == -1) return 1;
-    if (k.z == -1) return 2;
-    if (k.w == -1) return 3;
-    empty_hit = false;
-    return -1;
+    // selects, not branches: the first match, else the first empty slot
+    int m = k.w == key ? 3 : -1;
+    m = k.z == key ? 2 : m;
+    m = k.y == key ? 1 : m;
+    m = k.x == key ? 0 : m;
+    int f = k.w == -1 ? 3 : -1;
+    f = k.z == -1 ? 2 : f;
+    f = k.y == -1 ? 1 : f;
+    f = k.x == -1 ? 0 : f;
+    empty_hit = m < 0 && f >= 0;
+    return m >= 0 ? m : f;
 }
 
 // Insert key (and with NUM add x to its value); returns 1 if the key is new.

@@ -297,7 +297,8 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
             int col[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int c = cB[q[u]];                   // q is always a valid index
+                // lane 0 holds row u's first product: rows with none skip their load
+                const int c = __builtin_amdgcn_readfirstlane((int)ok[u]) ? cB[q[u]] : 0;   // q is a valid index
                 col[u] = ok[u] ? c : 0;
             }
             if (hc.bq == 1) {
@@ -849,8 +850,13 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
             V x[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int c = cB[q[u]];                       // q is always a valid index
-                const V b = vB[q[u]];
+                // lane 0 holds row u's first product: rows with none skip their loads
+                int c = 0;
+                V b = V(0);
+                if (__builtin_amdgcn_readfirstlane((int)ok[u])) {
+                    c = cB[q[u]];                             // q is a valid index
+                    b = vB[q[u]];
+                }
                 col[u] = ok[u] ? c : 0;
                 x[u] = ok[u] ? av[u] * b : V(0);
             }
