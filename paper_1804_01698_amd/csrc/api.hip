@@ -58,7 +58,7 @@ struct Prod {
     unsigned items_cap = 0;
     // workspace layout (offsets from the product's base)
     size_t ws_base = 0, ws_bytes = 0;
-    size_t o_hdr = 0, o_perm_sym = 0, o_perm_num = 0, o_nnz = 0, o_bsum = 0;
+    size_t o_hdr = 0, o_perm_sym = 0, o_prow_sym = 0, o_rows_num = 0, o_nnz = 0, o_bsum = 0;
     size_t o_chunk = 0, o_heavy = 0, o_items = 0, o_bc = 0, o_bv = 0, o_long = 0;
     size_t o_whist = 0, o_long_id = 0, o_idx = 0, o_slot = 0, o_bperm = 0, o_bmap = 0, o_bs = 0, o_ki = 0;
     bool store_bm = false;    // symbolic bitmaps kept for the numeric windows
@@ -324,7 +324,8 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
         q.ws_base = ws;
         q.o_hdr = o; o += align_up(WS_HDR_BYTES);
         q.o_perm_sym = o; o += align_up(4 * m);
-        q.o_perm_num = o; o += align_up(4 * m);
+        q.o_prow_sym = o; o += align_up(8 * m);
+        q.o_rows_num = o; o += align_up(sizeof(NumRow) * m);
         q.o_nnz = o; o += align_up(4 * m);
         q.o_bsum = o; o += align_up(8 * (nb + 1));
         q.o_slot = o; o += align_up(4 * m);
@@ -382,8 +383,8 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
         for (int b = 0; b < NSB; ++b) off.v[b] = q.sym_off[b];
         HIPCK(timed(pl, "sym_scatter", 8.0 * m,
                     [&] {
-                        return launch_sym_scatter(m, q.flop, q.B.ncols, off, perm, nnz, q.at<int32_t>(q.o_slot),
-                                                  q.wh, pl->lim, s);
+                        return launch_sym_scatter(m, q.flop, q.A.rpts, q.B.ncols, off, perm, q.at<int2>(q.o_prow_sym),
+                                                  nnz, q.at<int32_t>(q.o_slot), q.wh, pl->lim, s);
                     }),
               "sym_scatter");
         if (q.nbm > 0) {
@@ -422,7 +423,8 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
                 char name[32];
                 snprintf(name, sizeof(name), "sym_hash_%d", SYM_T[b]);
                 HIPCK(timed(pl, name, rows_bytes,
-                            [&] { return launch_sym_bin(b, nr, perm, off.v[b], q.A, q.B, nnz, q.wh, 
+                            [&] { return launch_sym_bin(b, nr, perm, q.at<int2>(q.o_prow_sym), off.v[b], q.A, q.B,
+                                                        nnz, q.wh,
                                                               HashCfg{pl->lim.hmul, pl->lim.bq, pl->count_probes, (uint32_t)b},
                                                               pl->ncu, s); }),
                       "sym_hash");
@@ -464,8 +466,8 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
         for (int b = 0; b < NNB; ++b) off.v[b] = q.num_off[b];
         HIPCK(timed(pl, "num_scatter", 8.0 * q.m,
                     [&] {
-                        return launch_num_scatter((int)q.m, q.at<int32_t>(q.o_nnz), q.flop, q.A.rpts, off,
-                                                  q.at<int32_t>(q.o_perm_num), q.wh, pl->lim, s);
+                        return launch_num_scatter((int)q.m, q.at<int32_t>(q.o_nnz), q.flop, q.A.rpts, q.rpts_C,
+                                                  off, q.at<NumRow>(q.o_rows_num), q.wh, pl->lim, s);
                     }),
               "num_scatter");
     }
@@ -515,7 +517,7 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
                         }),
                   "gather_B_vals");
         }
-        const int32_t *perm = q.at<int32_t>(q.o_perm_num);
+        const NumRow *rows = q.at<NumRow>(q.o_rows_num);
         for (int b = NUM_HEAVY_BIN - 1; b >= 1; --b) {
             const unsigned nr = (unsigned)q.hw.num_rows[b];
             if (nr == 0) continue;
@@ -525,7 +527,7 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
                                  12.0 * q.hw.num_nnzc[b];
             HIPCK(timed(pl, name, bytes,
                         [&] {
-                            return launch_num_bin(b, pl->dtype, sorted, nr, perm, q.num_off[b], q.A, q.B, q.rpts_C,
+                            return launch_num_bin(b, pl->dtype, sorted, nr, rows, q.num_off[b], q.A, q.B,
                                                   cols_C[p], vals_C[p], q.wh,
                                                   HashCfg{pl->lim.hmul, pl->lim.bq, pl->count_probes, (uint32_t)b},
                                                   pl->ncu, s);
@@ -539,7 +541,7 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
                                  12.0 * q.hw.num_nnzc[hb];
             HIPCK(timed(pl, "num_heap", bytes,
                         [&] {
-                            return launch_num_heap(pl->dtype, nr, perm, q.num_off[hb], q.A, q.B, q.rpts_C, cols_C[p],
+                            return launch_num_heap(pl->dtype, nr, rows, q.num_off[hb], q.A, q.B, cols_C[p],
                                                    vals_C[p], q.wh, s);
                         }),
                   "num_heap");

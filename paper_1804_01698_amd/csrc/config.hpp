@@ -197,6 +197,15 @@ struct WinItem {
 // whole chunks per row) are kept when they take at most this many bytes.
 constexpr unsigned long long BM_STORE_MAX = 64ull << 30;
 
+// A row of a numeric hash or heap bin list: its entries of A [a0, a1), and
+// out_n = (position of the row in C) << 16 | nnz(c_i) (those bins hold rows
+// of at most WIN_CAP < 2^16 entries).
+struct alignas(16) NumRow {
+    int32_t a0, a1;
+    uint64_t out_n;
+};
+static_assert(WIN_CAP < (1 << 16), "nnz(c_i) of a listed row fits 16 bits");
+
 struct HeavyRow {
     int32_t row;
     int32_t slot;       // index of the row within the bitmap bin (chunk-count slot)

@@ -145,8 +145,9 @@ __global__ __launch_bounds__(256) void k_count_long_b(int n, const int32_t *__re
 // ----------------------------------------------------------------------- binning
 
 __global__ __launch_bounds__(256) void k_sym_scatter(int m, const uint32_t *__restrict__ flop,
+                                                     const int32_t *__restrict__ rA,
                                                      int64_t ncolsB, BinOffsets off,
-                                                     int32_t *__restrict__ perm,
+                                                     int32_t *__restrict__ perm, int2 *__restrict__ prow,
                                                      int32_t *__restrict__ nnz_row,
                                                      int32_t *__restrict__ slot_of, WsHdr *wh, BinLimits L) {
     __shared__ unsigned int s_cnt[NSB], s_base[NSB];
@@ -164,7 +165,10 @@ __global__ __launch_bounds__(256) void k_sym_scatter(int m, const uint32_t *__re
     __syncthreads();
     if (tid < NSB && s_cnt[tid]) s_base[tid] = atomicAdd(&wh->sym_cursor[tid], s_cnt[tid]);
     __syncthreads();
-    if (b > 0) perm[off.v[b] + s_base[b] + r] = i;
+    if (b > 0) {
+        perm[off.v[b] + s_base[b] + r] = i;
+        prow[off.v[b] + s_base[b] + r] = make_int2(rA[i], rA[i + 1]);
+    }
     if (b == SYM_BITMAP_BIN) {
         nnz_row[i] = 0;                       // summed over the row's work items
         slot_of[i] = (int32_t)(s_base[b] + r);
@@ -203,7 +207,8 @@ __global__ __launch_bounds__(256) void k_num_hist(int m, const int32_t *__restri
 __global__ __launch_bounds__(256) void k_num_scatter(int m, const int32_t *__restrict__ nnz_row,
                                                      const uint32_t *__restrict__ flop,
                                                      const int32_t *__restrict__ rA,
-                                                     BinOffsets off, int32_t *__restrict__ perm,
+                                                     const int64_t *__restrict__ rpts_C,
+                                                     BinOffsets off, NumRow *__restrict__ rows,
                                                      WsHdr *wh, BinLimits L) {
     __shared__ unsigned int s_cnt[NNB], s_base[NNB];
     const int tid = threadIdx.x;
@@ -220,7 +225,9 @@ __global__ __launch_bounds__(256) void k_num_scatter(int m, const int32_t *__res
     __syncthreads();
     if (tid < NNB && s_cnt[tid]) s_base[tid] = atomicAdd(&wh->num_cursor[tid], s_cnt[tid]);
     __syncthreads();
-    if (b > 0) perm[off.v[b] + s_base[b] + r] = i;
+    if (b > 0)
+        rows[off.v[b] + s_base[b] + r] =
+            NumRow{rA[i], rA[i + 1], ((unsigned long long)rpts_C[i] << 16) | (unsigned)nnz_row[i]};
 }
 
 // ----------------------------------------------------------------------- row prefetch
@@ -237,9 +244,9 @@ struct RowPre {
 };
 
 template <int G, bool NUM, typename V>
-__device__ __forceinline__ RowPre<V> row_pre_entry(int row, const int32_t *__restrict__ rA,
-                                                   const int32_t *__restrict__ cA, const V *__restrict__ vA) {
-    RowPre<V> p{row, rA[row], rA[row + 1], -1, 0, 0, V(0)};
+__device__ __forceinline__ RowPre<V> row_pre_entry(int row, int a0, int a1, const int32_t *__restrict__ cA,
+                                                   const V *__restrict__ vA) {
+    RowPre<V> p{row, a0, a1, -1, 0, 0, V(0)};
     const int e = p.a0 + (int)threadIdx.x;
     if (p.a1 - p.a0 <= G && e < p.a1) {
         p.k = cA[e];
@@ -257,9 +264,9 @@ __device__ __forceinline__ void row_pre_slice(RowPre<V> &p, const int32_t *__res
 }
 
 template <int G, bool NUM, typename V>
-__device__ __forceinline__ RowPre<V> row_pre(int row, const int32_t *__restrict__ rA, const int32_t *__restrict__ cA,
+__device__ __forceinline__ RowPre<V> row_pre(int row, int a0, int a1, const int32_t *__restrict__ cA,
                                              const V *__restrict__ vA, const int32_t *__restrict__ rB) {
-    RowPre<V> p = row_pre_entry<G, NUM, V>(row, rA, cA, vA);
+    RowPre<V> p = row_pre_entry<G, NUM, V>(row, a0, a1, cA, vA);
     row_pre_slice(p, rB);
     return p;
 }
@@ -267,8 +274,8 @@ __device__ __forceinline__ RowPre<V> row_pre(int row, const int32_t *__restrict_
 // ----------------------------------------------------------------------- symbolic
 
 template <int G, int T, int U, bool PERSIST>
-__global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm, int64_t perm_off, unsigned nrows,
-                                                const int32_t *__restrict__ rA,
+__global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm, const int2 *__restrict__ prow,
+                                                int64_t perm_off, unsigned nrows,
                                                 const int32_t *__restrict__ cA,
                                                 const int32_t *__restrict__ rB,
                                                 const int32_t *__restrict__ cB,
@@ -280,9 +287,13 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
     const unsigned step = PERSIST ? gridDim.x : nrows;
     unsigned it = blockIdx.x;
     if (it >= nrows) return;                              // uniform over the block
+    // the bin list gives the row and its A range side by side (no dependent load)
     RowPre<double> cur;
-    if constexpr (PERSIST) cur = row_pre<G, false, double>(perm[perm_off + it], rA, cA, nullptr, rB);
-    else cur = RowPre<double>{perm[perm_off + it], 0, 0, -1, 0, 0, 0.0};
+    {
+        const int2 ar = prow[perm_off + it];
+        if constexpr (PERSIST) cur = row_pre<G, false, double>(perm[perm_off + it], ar.x, ar.y, cA, nullptr, rB);
+        else cur = RowPre<double>{perm[perm_off + it], ar.x, ar.y, -1, 0, 0, 0.0};
+    }
     while (true) {
         const int row = cur.row;
         table_clear<G, T, false, double>(tab, nullptr);
@@ -290,7 +301,10 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
         const unsigned nit = it + step;
         RowPre<double> nxt{};
         if constexpr (PERSIST)
-            if (nit < nrows) nxt = row_pre_entry<G, false, double>(perm[perm_off + nit], rA, cA, nullptr);
+            if (nit < nrows) {
+                const int2 ar = prow[perm_off + nit];
+                nxt = row_pre_entry<G, false, double>(perm[perm_off + nit], ar.x, ar.y, cA, nullptr);
+            }
         int cnt = 0, ovf = 0;
         unsigned prb = 0;
         auto act = [&](const int (&q)[U], const bool (&ok)[U], const double (&)[U]) {
@@ -314,7 +328,7 @@ __global__ __launch_bounds__(G) void k_sym_hash(const int32_t *__restrict__ perm
         auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
         if (PERSIST && cur.a1 - cur.a0 <= G) enum_chunk<G, U, false, double>(cur.lo, cur.hi - cur.lo, 0.0, sg, act);
         else if (PERSIST) enum_row<G, U, false, double>(cur.a0, cur.a1, cA, nullptr, sg, slice, act);
-        else enum_row<G, U, false, double>(rA[row], rA[row + 1], cA, nullptr, sg, slice, act);
+        else enum_row<G, U, false, double>(cur.a0, cur.a1, cA, nullptr, sg, slice, act);
         __syncthreads();
         if constexpr (PERSIST)
             if (nit < nrows) row_pre_slice(nxt, rB);
@@ -367,7 +381,11 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
     // the bitmap is clear at the start of every pass: cleared once here, then
     // by the last phase that reads it
     for (int i = tid; i < NWORDS / 4; i += G) bm4[i] = u32x4{0u, 0u, 0u, 0u};
-    RowPre<double> cur = row_pre<G, false, double>(perm[perm_off + slot], rA, cA, nullptr, rB);
+    RowPre<double> cur;
+    {
+        const int r0 = perm[perm_off + slot];
+        cur = row_pre<G, false, double>(r0, rA[r0], rA[r0 + 1], cA, nullptr, rB);
+    }
     const int npass = (int)((ncols + WIN - 1) / WIN);
     auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
     while (true) {
@@ -377,7 +395,10 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
         // the next row's A entries are loaded while this row's products run
         const unsigned nslot = slot + gridDim.x;
         RowPre<double> nxt{};
-        if (nslot < nrows) nxt = row_pre_entry<G, false, double>(perm[perm_off + nslot], rA, cA, nullptr);
+        if (nslot < nrows) {
+            const int r1 = perm[perm_off + nslot];
+            nxt = row_pre_entry<G, false, double>(r1, rA[r1], rA[r1 + 1], cA, nullptr);
+        }
         for (int pass = 0; pass < npass; ++pass) {
             const int64_t c0 = (int64_t)pass * WIN;
             const uint32_t wcols = (uint32_t)(ncols - c0 < WIN ? ncols - c0 : WIN);
@@ -811,14 +832,12 @@ struct NumLds {
 };
 
 template <int G, int T, int U, bool SORTED, typename V, bool PERSIST>
-__global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm, int64_t perm_off, unsigned nrows,
-                                                const int32_t *__restrict__ rA,
+__global__ __launch_bounds__(G) void k_num_hash(const NumRow *__restrict__ rows, int64_t perm_off, unsigned nrows,
                                                 const int32_t *__restrict__ cA,
                                                 const V *__restrict__ vA,
                                                 const int32_t *__restrict__ rB,
                                                 const int32_t *__restrict__ cB,
                                                 const V *__restrict__ vB,
-                                                const int64_t *__restrict__ rpts_C,
                                                 int32_t *__restrict__ cC, V *__restrict__ vC,
                                                 WsHdr *wh, HashCfg hc, int64_t ncolsB) {
     __shared__ __align__(16) int keys[T];
@@ -831,18 +850,24 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
     const unsigned step = PERSIST ? gridDim.x : nrows;
     unsigned it = blockIdx.x;
     if (it >= nrows) return;                                  // uniform over the block
+    // the bin list gives each row's A range and place in C (no dependent load);
+    // RowPre.row carries the list index
+    NumRow nr = rows[perm_off + it];
     RowPre<V> cur;
-    if constexpr (PERSIST) cur = row_pre<G, true, V>(perm[perm_off + it], rA, cA, vA, rB);
-    else cur = RowPre<V>{perm[perm_off + it], 0, 0, -1, 0, 0, V(0)};
+    if constexpr (PERSIST) cur = row_pre<G, true, V>((int)it, nr.a0, nr.a1, cA, vA, rB);
+    else cur = RowPre<V>{(int)it, nr.a0, nr.a1, -1, 0, 0, V(0)};
     while (true) {
-        const int row = cur.row;
         table_clear<G, T, true, V>(keys, vals);
         __syncthreads();
         // the next row's A entries are loaded while this row's products run
         const unsigned nit = it + step;
         RowPre<V> nxt{};
+        NumRow nnr{};
         if constexpr (PERSIST)
-            if (nit < nrows) nxt = row_pre_entry<G, true, V>(perm[perm_off + nit], rA, cA, vA);
+            if (nit < nrows) {
+                nnr = rows[perm_off + nit];
+                nxt = row_pre_entry<G, true, V>((int)nit, nnr.a0, nnr.a1, cA, vA);
+            }
         int ovf = 0;
         unsigned prb = 0;
         auto act = [&](const int (&q)[U], const bool (&ok)[U], const V (&av)[U]) {
@@ -873,7 +898,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
         auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
         if (PERSIST && cur.a1 - cur.a0 <= G) enum_chunk<G, U, true, V>(cur.lo, cur.hi - cur.lo, cur.a, sg, act);
         else if (PERSIST) enum_row<G, U, true, V>(cur.a0, cur.a1, cA, vA, sg, slice, act);
-        else enum_row<G, U, true, V>(rA[row], rA[row + 1], cA, vA, sg, slice, act);
+        else enum_row<G, U, true, V>(cur.a0, cur.a1, cA, vA, sg, slice, act);
         __syncthreads();
         if constexpr (PERSIST)
             if (nit < nrows) row_pre_slice(nxt, rB);          // and then the slices of their B rows
@@ -885,8 +910,8 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
             const unsigned long long t = wave_sum_u64(prb);
             if ((tid & 63) == 0 && t) atomicAdd(&wh->num_probes[hc.bin], t);
         }
-        const int64_t o = rpts_C[row];
-        const int expected = (int)(rpts_C[row + 1] - o);
+        const int64_t o = (int64_t)(nr.out_n >> 16);
+        const int expected = (int)(nr.out_n & 0xFFFFu);
         bool ranked = false;
         if constexpr (SORTED && G >= 512) {
             // Sorted output of a wide bin by rank instead of a bitonic sort: the
@@ -952,6 +977,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const int32_t *__restrict__ perm
         __syncthreads();                                      // the table is reused by the next row
         it = nit;
         cur = nxt;
+        nr = nnr;
     }
 }
 
@@ -1306,12 +1332,11 @@ __global__ __launch_bounds__(256) void k_check_sorted(int64_t nnz, const int32_t
 // leave in ascending column order, 64 per coalesced store.  The B rows must be
 // sorted (checked when the plan is made).
 template <typename V>
-__global__ __launch_bounds__(64) void k_num_heap(const int32_t *__restrict__ perm, int64_t perm_off, unsigned nrows,
-                                                 const int32_t *__restrict__ rA, const int32_t *__restrict__ cA,
+__global__ __launch_bounds__(64) void k_num_heap(const NumRow *__restrict__ rows, int64_t perm_off, unsigned nrows,
+                                                 const int32_t *__restrict__ cA,
                                                  const V *__restrict__ vA, const int32_t *__restrict__ rB,
                                                  const int32_t *__restrict__ cB, const V *__restrict__ vB,
-                                                 const int64_t *__restrict__ rpts_C, int32_t *__restrict__ cC,
-                                                 V *__restrict__ vC, WsHdr *wh) {
+                                                 int32_t *__restrict__ cC, V *__restrict__ vC, WsHdr *wh) {
     constexpr int NQ = HEAP_MAX_A / WAVE;       // queue slots per lane
     constexpr int NONE = 0x7FFFFFFF;            // head of an exhausted slice
     __shared__ int scol[HEAP_FCAP];
@@ -1320,8 +1345,8 @@ __global__ __launch_bounds__(64) void k_num_heap(const int32_t *__restrict__ per
     __shared__ int slo[HEAP_MAX_A];
     const int ln = threadIdx.x;
     if (blockIdx.x >= nrows) return;
-    const int row = perm[perm_off + blockIdx.x];
-    const int a0 = rA[row], a1 = rA[row + 1];
+    const NumRow nr = rows[perm_off + blockIdx.x];
+    const int a0 = nr.a0, a1 = nr.a1;
     // the slices of the row's entries, laid end to end in LDS (entry a0 + s
     // owns positions [soff[s], soff[s] + len))
     int cur[NQ], end[NQ];
@@ -1361,8 +1386,8 @@ __global__ __launch_bounds__(64) void k_num_heap(const int32_t *__restrict__ per
     int head[NQ];
 #pragma unroll
     for (int t = 0; t < NQ; ++t) head[t] = cur[t] < end[t] ? scol[cur[t]] : NONE;
-    const int64_t o = rpts_C[row];
-    const int expected = (int)(rpts_C[row + 1] - o);
+    const int64_t o = (int64_t)(nr.out_n >> 16);
+    const int expected = (int)(nr.out_n & 0xFFFFu);
     int nout = 0;                               // entries emitted (wave-uniform)
     int last = -1;                              // column of the pending entry (wave-uniform)
     V pend = V(0);
@@ -1665,38 +1690,38 @@ hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, uin
     return hipGetLastError();
 }
 
-hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const BinOffsets &off,
-                              int32_t *perm, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh, const BinLimits &L,
-                              hipStream_t s) {
+hipError_t launch_sym_scatter(int m, const uint32_t *flop, const int32_t *rA, int64_t ncolsB, const BinOffsets &off,
+                              int32_t *perm, int2 *prow, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh,
+                              const BinLimits &L, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    k_sym_scatter<<<grid1(m, 256), 256, 0, s>>>(m, flop, ncolsB, off, perm, nnz_row, slot_of, wh, L);
+    k_sym_scatter<<<grid1(m, 256), 256, 0, s>>>(m, flop, rA, ncolsB, off, perm, prow, nnz_row, slot_of, wh, L);
     return hipGetLastError();
 }
 
 template <int G, int T>
-static void sym_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
+static void sym_hash_l(unsigned nrows, const int32_t *perm, const int2 *prow, int64_t off, const CsrDev &A,
                        const CsrDev &B, int32_t *nnz_row, WsHdr *wh, HashCfg hc, int ncu, hipStream_t s) {
     constexpr int U = u_for(G, T / 2 + 1);
     // wide bins (few blocks per CU) run persistent; narrow ones a block per row
     constexpr bool P = G >= 512;
     static const int occ = P ? blocks_per_cu(k_sym_hash<G, T, U, P>, G) : 0;
     const unsigned grid = P ? (unsigned)std::min<int64_t>(nrows, (int64_t)ncu * occ) : nrows;
-    k_sym_hash<G, T, U, P><<<grid, G, 0, s>>>(perm, off, nrows, A.rpts, A.cols, B.rpts, B.cols, nnz_row, wh, hc);
+    k_sym_hash<G, T, U, P><<<grid, G, 0, s>>>(perm, prow, off, nrows, A.cols, B.rpts, B.cols, nnz_row, wh, hc);
 }
 
-hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
+hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, const int2 *prow, int64_t off, const CsrDev &A,
                           const CsrDev &B, int32_t *nnz_row, WsHdr *wh, HashCfg hc, int ncu, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     switch (bin) {
-        case 1: sym_hash_l<SYM_G[1], SYM_T[1]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
-        case 2: sym_hash_l<SYM_G[2], SYM_T[2]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
-        case 3: sym_hash_l<SYM_G[3], SYM_T[3]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
-        case 4: sym_hash_l<SYM_G[4], SYM_T[4]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
-        case 5: sym_hash_l<SYM_G[5], SYM_T[5]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
-        case 6: sym_hash_l<SYM_G[6], SYM_T[6]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
-        case 7: sym_hash_l<SYM_G[7], SYM_T[7]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
-        case 8: sym_hash_l<SYM_G[8], SYM_T[8]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
-        case 9: sym_hash_l<SYM_G[9], SYM_T[9]>(nrows, perm, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 1: sym_hash_l<SYM_G[1], SYM_T[1]>(nrows, perm, prow, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 2: sym_hash_l<SYM_G[2], SYM_T[2]>(nrows, perm, prow, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 3: sym_hash_l<SYM_G[3], SYM_T[3]>(nrows, perm, prow, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 4: sym_hash_l<SYM_G[4], SYM_T[4]>(nrows, perm, prow, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 5: sym_hash_l<SYM_G[5], SYM_T[5]>(nrows, perm, prow, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 6: sym_hash_l<SYM_G[6], SYM_T[6]>(nrows, perm, prow, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 7: sym_hash_l<SYM_G[7], SYM_T[7]>(nrows, perm, prow, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 8: sym_hash_l<SYM_G[8], SYM_T[8]>(nrows, perm, prow, off, A, B, nnz_row, wh, hc, ncu, s); break;
+        case 9: sym_hash_l<SYM_G[9], SYM_T[9]>(nrows, perm, prow, off, A, B, nnz_row, wh, hc, ncu, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1790,55 +1815,53 @@ hipError_t launch_entry_brow(const CsrDev &A, const CsrDev &B, const int32_t *lo
 }
 
 hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
-                              const BinOffsets &off, int32_t *perm, WsHdr *wh, const BinLimits &L, hipStream_t s) {
+                              const int64_t *rpts_C, const BinOffsets &off, NumRow *rows, WsHdr *wh,
+                              const BinLimits &L, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    k_num_scatter<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, flop, rA, off, perm, wh, L);
+    k_num_scatter<<<grid1(m, 256), 256, 0, s>>>(m, nnz_row, flop, rA, rpts_C, off, rows, wh, L);
     return hipGetLastError();
 }
 
 template <int G, int T, bool SORTED, typename V>
-static void num_hash_l(unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                       const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, HashCfg hc, int ncu,
-                       hipStream_t s) {
+static void num_hash_l(unsigned nrows, const NumRow *rows, int64_t off, const CsrDev &A, const CsrDev &B,
+                       int32_t *cC, void *vC, WsHdr *wh, HashCfg hc, int ncu, hipStream_t s) {
     constexpr int U = u_for(G, T / 2 + 1) < 4 ? u_for(G, T / 2 + 1) : 4;
     // wide bins (few blocks per CU) run persistent; narrow ones a block per row
     constexpr bool P = G >= 512;
     static const int occ = P ? blocks_per_cu(k_num_hash<G, T, U, SORTED, V, P>, G) : 0;
     const unsigned grid = P ? (unsigned)std::min<int64_t>(nrows, (int64_t)ncu * occ) : nrows;
-    k_num_hash<G, T, U, SORTED, V, P><<<grid, G, 0, s>>>(perm, off, nrows, A.rpts, A.cols, (const V *)A.vals, B.rpts,
-                                                    B.cols, (const V *)B.vals, rpts_C, cC, (V *)vC, wh, hc,
-                                                    B.ncols);
+    k_num_hash<G, T, U, SORTED, V, P><<<grid, G, 0, s>>>(rows, off, nrows, A.cols, (const V *)A.vals, B.rpts,
+                                                    B.cols, (const V *)B.vals, cC, (V *)vC, wh, hc, B.ncols);
 }
 
 template <bool SORTED, typename V>
-static hipError_t num_bin_t(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                            const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh,
-                            HashCfg hc, int ncu, hipStream_t s) {
+static hipError_t num_bin_t(int bin, unsigned nrows, const NumRow *rows, int64_t off, const CsrDev &A,
+                            const CsrDev &B, int32_t *cC, void *vC, WsHdr *wh, HashCfg hc, int ncu,
+                            hipStream_t s) {
     switch (bin) {
-        case 1: num_hash_l<NUM_G[1], NUM_T[1], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
-        case 2: num_hash_l<NUM_G[2], NUM_T[2], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
-        case 3: num_hash_l<NUM_G[3], NUM_T[3], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
-        case 4: num_hash_l<NUM_G[4], NUM_T[4], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
-        case 5: num_hash_l<NUM_G[5], NUM_T[5], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
-        case 6: num_hash_l<NUM_G[6], NUM_T[6], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
-        case 7: num_hash_l<NUM_G[7], NUM_T[7], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
-        case 8: num_hash_l<NUM_G[8], NUM_T[8], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
-        case 9: num_hash_l<NUM_G[9], NUM_T[9], SORTED, V>(nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s); break;
+        case 1: num_hash_l<NUM_G[1], NUM_T[1], SORTED, V>(nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s); break;
+        case 2: num_hash_l<NUM_G[2], NUM_T[2], SORTED, V>(nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s); break;
+        case 3: num_hash_l<NUM_G[3], NUM_T[3], SORTED, V>(nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s); break;
+        case 4: num_hash_l<NUM_G[4], NUM_T[4], SORTED, V>(nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s); break;
+        case 5: num_hash_l<NUM_G[5], NUM_T[5], SORTED, V>(nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s); break;
+        case 6: num_hash_l<NUM_G[6], NUM_T[6], SORTED, V>(nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s); break;
+        case 7: num_hash_l<NUM_G[7], NUM_T[7], SORTED, V>(nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s); break;
+        case 8: num_hash_l<NUM_G[8], NUM_T[8], SORTED, V>(nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s); break;
+        case 9: num_hash_l<NUM_G[9], NUM_T[9], SORTED, V>(nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
-                          const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
-                          WsHdr *wh, HashCfg hc, int ncu, hipStream_t s) {
+hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const NumRow *rows, int64_t off,
+                          const CsrDev &A, const CsrDev &B, int32_t *cC, void *vC, WsHdr *wh, HashCfg hc, int ncu,
+                          hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     if (dtype == 0)
-        return sorted ? num_bin_t<true, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s)
-                      : num_bin_t<false, double>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s);
-    return sorted ? num_bin_t<true, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu, s)
-                  : num_bin_t<false, unsigned long long>(bin, nrows, perm, off, A, B, rpts_C, cC, vC, wh, hc, ncu,
-                                                         s);
+        return sorted ? num_bin_t<true, double>(bin, nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s)
+                      : num_bin_t<false, double>(bin, nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s);
+    return sorted ? num_bin_t<true, unsigned long long>(bin, nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s)
+                  : num_bin_t<false, unsigned long long>(bin, nrows, rows, off, A, B, cC, vC, wh, hc, ncu, s);
 }
 
 __global__ void k_zero_u32n(unsigned *p, int n) {
@@ -1874,16 +1897,16 @@ hipError_t launch_check_sorted(const CsrDev &B, int *err, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_num_heap(int dtype, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                           const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s) {
+hipError_t launch_num_heap(int dtype, unsigned nrows, const NumRow *rows, int64_t off, const CsrDev &A,
+                           const CsrDev &B, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     if (dtype == 0)
-        k_num_heap<double><<<nrows, WAVE, 0, s>>>(perm, off, nrows, A.rpts, A.cols, (const double *)A.vals, B.rpts,
-                                                  B.cols, (const double *)B.vals, rpts_C, cC, (double *)vC, wh);
+        k_num_heap<double><<<nrows, WAVE, 0, s>>>(rows, off, nrows, A.cols, (const double *)A.vals, B.rpts,
+                                                  B.cols, (const double *)B.vals, cC, (double *)vC, wh);
     else
         k_num_heap<unsigned long long><<<nrows, WAVE, 0, s>>>(
-            perm, off, nrows, A.rpts, A.cols, (const unsigned long long *)A.vals, B.rpts, B.cols,
-            (const unsigned long long *)B.vals, rpts_C, cC, (unsigned long long *)vC, wh);
+            rows, off, nrows, A.cols, (const unsigned long long *)A.vals, B.rpts, B.cols,
+            (const unsigned long long *)B.vals, cC, (unsigned long long *)vC, wh);
     return hipGetLastError();
 }
 

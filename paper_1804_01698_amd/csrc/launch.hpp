@@ -24,10 +24,10 @@ struct BinOffsets {
 hipError_t launch_validate(const CsrDev &a, int *err, hipStream_t s);
 hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, uint32_t *edeg, PlanHdr *hdr,
                            const BinLimits &L, hipStream_t s);
-hipError_t launch_sym_scatter(int m, const uint32_t *flop, int64_t ncolsB, const BinOffsets &off,
-                              int32_t *perm, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh, const BinLimits &L,
-                              hipStream_t s);
-hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
+hipError_t launch_sym_scatter(int m, const uint32_t *flop, const int32_t *rA, int64_t ncolsB, const BinOffsets &off,
+                              int32_t *perm, int2 *prow, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh,
+                              const BinLimits &L, hipStream_t s);
+hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, const int2 *prow, int64_t off, const CsrDev &A,
                           const CsrDev &B, int32_t *nnz_row, WsHdr *wh, HashCfg hc, int ncu, hipStream_t s);
 hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
                                int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, int ncu,
@@ -44,13 +44,14 @@ hipError_t launch_bucket(const CsrDev &B, int32_t *bc, int32_t *bperm, int32_t *
                          int32_t *long_list, int32_t *idx, int nchunks, WsHdr *wh, hipStream_t s);
 hipError_t launch_gather_vals(int dtype, int64_t n, const int32_t *bperm, const void *vB, void *bv, hipStream_t s);
 hipError_t launch_num_scatter(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
-                              const BinOffsets &off, int32_t *perm, WsHdr *wh, const BinLimits &L, hipStream_t s);
+                              const int64_t *rpts_C, const BinOffsets &off, NumRow *rows, WsHdr *wh,
+                              const BinLimits &L, hipStream_t s);
 hipError_t launch_check_sorted(const CsrDev &B, int *err, hipStream_t s);
-hipError_t launch_num_heap(int dtype, unsigned nrows, const int32_t *perm, int64_t off, const CsrDev &A,
-                           const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s);
-hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const int32_t *perm, int64_t off,
-                          const CsrDev &A, const CsrDev &B, const int64_t *rpts_C, int32_t *cC, void *vC,
-                          WsHdr *wh, HashCfg hc, int ncu, hipStream_t s);
+hipError_t launch_num_heap(int dtype, unsigned nrows, const NumRow *rows, int64_t off, const CsrDev &A,
+                           const CsrDev &B, int32_t *cC, void *vC, WsHdr *wh, hipStream_t s);
+hipError_t launch_num_bin(int bin, int dtype, bool sorted, unsigned nrows, const NumRow *rows, int64_t off,
+                          const CsrDev &A, const CsrDev &B, int32_t *cC, void *vC, WsHdr *wh, HashCfg hc, int ncu,
+                          hipStream_t s);
 hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const int2 *ki,
                              const int32_t *idx, int nchunks, const int32_t *bc, const void *bv, int32_t *cC,
                              void *vC, const uint32_t *bmap, WsHdr *wh, int ncu, hipStream_t s);
