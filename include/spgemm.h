@@ -109,7 +109,7 @@ typedef struct spgemm_plan_s *spgemm_plan_t;
 /*
  * Bytes of device "plan scratch" spgemm_plan needs for nprod products whose
  * left operands are A[0..nprod-1] (a small header, 4 bytes per row of A for
- * the row flop and 4 bytes per entry of A used while planning).
+ * the row flop and a list of the rows of A longer than 4096 entries).
  * Returns 0 if an argument is invalid.
  */
 size_t spgemm_plan_scratch_bytes(int nprod, const spgemm_csr *A);

@@ -50,7 +50,6 @@ struct Prod {
     char *ps = nullptr;
     PlanHdr *phdr = nullptr;
     uint32_t *flop = nullptr;
-    uint32_t *edeg = nullptr;   // per entry of A: length of the B row it selects
     PlanHdr h{};
     int64_t sym_off[NSB]{};
     int64_t nbm = 0;          // rows in the bitmap bin
@@ -143,7 +142,7 @@ bool limits_from(const spgemm_config *cfg, BinLimits *L) {
 
 // header, per-row flop (uint32), per-entry B row length (uint32, plan time only)
 size_t plan_scratch_one(int64_t m, int64_t nnz) {
-    return PLAN_HDR_BYTES + align_up((size_t)m * 4) + align_up((size_t)nnz * 4);
+    return PLAN_HDR_BYTES + align_up((size_t)m * 4) + align_up((size_t)(nnz / (FLOP_WAVE_ROW + 1)) * 4);
 }
 
 // Workspace of spgemm_symbolic_static.  Each GPU the library runs on holds
@@ -265,7 +264,6 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
         q.ps = ps;
         q.phdr = (PlanHdr *)ps;
         q.flop = (uint32_t *)(ps + PLAN_HDR_BYTES);
-        q.edeg = (uint32_t *)(ps + PLAN_HDR_BYTES + align_up((size_t)q.m * 4));
         ps += plan_scratch_one(q.m, q.A.nnz);
         hipError_t e = hipMemsetAsync(q.phdr, 0, sizeof(PlanHdr), stream);
         if (e != hipSuccess) return fail(hip_fail(e, "hipMemsetAsync(plan header)"));
@@ -289,8 +287,9 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     }
     for (int p = 0; p < nprod; ++p) {
         Prod &q = pl->prods[p];
+        int32_t *huge = (int32_t *)(q.ps + PLAN_HDR_BYTES + align_up((size_t)q.m * 4));   // after the row flop
         hipError_t e = timed(pl, "row_flop", 12.0 * q.A.nnz + 8.0 * q.m,
-                             [&] { return launch_row_flop(q.A, q.B, q.flop, q.edeg, q.phdr, pl->lim, stream); });
+                             [&] { return launch_row_flop(q.A, q.B, q.flop, huge, q.phdr, pl->lim, stream); });
         if (e == hipSuccess) e = launch_count_long_b(q.B, q.phdr, stream);
         if (e == hipSuccess && pl->lim.heap) e = launch_check_sorted(q.B, &q.phdr->err, stream);
         if (e != hipSuccess) return fail(hip_fail(e, "row_flop"));

@@ -158,8 +158,14 @@ struct PlanHdr {
     unsigned long long sym_flop[NSB];
     unsigned long long sym_nnza[NSB];
     int err;
-    int pad_[7];
+    unsigned n_huge;               // rows of A longer than FLOP_WAVE_ROW (listed for k_huge_flop)
+    int pad_[6];
 };
+
+// Row flop: rows of A with more than FLOP_WAVE_ROW entries are summed by a
+// block of their own after the pass over all rows; the plan scratch lists
+// them (at most nnz(A) / (FLOP_WAVE_ROW + 1) rows).
+constexpr int FLOP_WAVE_ROW = 4096;
 
 struct WsHdr {
     unsigned long long nnz_c;

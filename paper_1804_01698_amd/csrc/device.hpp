@@ -20,9 +20,10 @@ __device__ __forceinline__ void wave_sync() {
 
 // Value of x from another lane by a DPP move (VALU only, no LDS): lanes
 // whose source lies outside the pattern, or whose row is outside ROW_MASK,
-// get 0.  CTRL 0x110+n = shift right by n within each row of 16 lanes;
-// 0x142 = lane 15 of each row to the whole next row; 0x143 = lane 31 to the
-// rows above it.
+// get 0.  CTRL 0x00..0xFF = a permutation inside each quad of lanes (2 bits
+// per lane); 0x110+n = shift right by n within each row of 16 lanes; 0x142 =
+// lane 15 of each row to the whole next row; 0x143 = lane 31 to the rows
+// above it.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ int dpp_i32(int x) {
     return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xF, false);

@@ -63,20 +63,32 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nrows, int64_t ncols, 
 // block: a row of at most 64 entries is summed by its own thread (contiguous
 // reads); longer rows (the hub rows of skewed inputs) are summed by the whole
 // block in turn, so no block waits on a long chain of dependent loads.
-__global__ __launch_bounds__(256) void k_entry_deg(int64_t nnz, const int32_t *__restrict__ cA,
-                                                   const int32_t *__restrict__ rB, uint32_t *__restrict__ edeg) {
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nnz; e += stride) {
-        const int k = cA[e];
-        edeg[e] = (uint32_t)(rB[k + 1] - rB[k]);
-    }
+constexpr int FLOP_SHORT_ROW = 32;
+
+// Length of the B row that entry p of A selects.
+__device__ __forceinline__ uint32_t entry_deg(int p, const int32_t *__restrict__ cA, const int32_t *__restrict__ rB) {
+    const int k = cA[p];
+    return (uint32_t)(rB[k + 1] - rB[k]);
 }
 
-constexpr int FLOP_SHORT_ROW = 64;
+// Row flop, key bound bin and the plan header's per-bin totals of a row.
+__device__ __forceinline__ void row_flop_put(int row, unsigned long long f, int na, int64_t ncolsB,
+                                             uint32_t *__restrict__ flop_out, unsigned long long *rows,
+                                             unsigned long long *flop, unsigned long long *nnza,
+                                             unsigned long long *tot, unsigned long long *mx, const BinLimits &L) {
+    flop_out[row] = f > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)f;
+    const int b = sym_bin_l(f, ncolsB, L);
+    atomicAdd(&rows[b], 1ull);
+    atomicAdd(&flop[b], f);
+    atomicAdd(&nnza[b], (unsigned long long)na);
+    atomicAdd(tot, f);
+    atomicMax(mx, f);
+}
 
 __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restrict__ rA,
-                                                  const uint32_t *__restrict__ edeg, int64_t ncolsB,
-                                                  uint32_t *__restrict__ flop_out, PlanHdr *hdr, BinLimits L) {
+                                                  const int32_t *__restrict__ cA, const int32_t *__restrict__ rB,
+                                                  int64_t ncolsB, uint32_t *__restrict__ flop_out,
+                                                  int32_t *__restrict__ huge, PlanHdr *hdr, BinLimits L) {
     __shared__ unsigned long long s_f[256];
     __shared__ int s_long[256];
     __shared__ int s_nlong;
@@ -94,33 +106,42 @@ __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restri
         a0 = rA[r0 + tid];
         a1 = rA[r0 + tid + 1];
         if (a1 - a0 <= FLOP_SHORT_ROW) {
-            for (int p = a0; p < a1; ++p) f += edeg[p];
+            int p = a0;
+            for (; p + 8 <= a1; p += 8) {              // eight entries' loads in flight
+                unsigned long long d = 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) d += entry_deg(p + u, cA, rB);
+                f += d;
+            }
+            for (; p < a1; ++p) f += entry_deg(p, cA, rB);
         } else {
             s_long[atomicAdd(&s_nlong, 1)] = tid;
         }
     }
     s_f[tid] = f;
     __syncthreads();
+    // rows longer than FLOP_SHORT_ROW entries: one wave each, in steps of 64
+    // entries with four steps' loads in flight; rows longer than
+    // FLOP_WAVE_ROW go to the list of k_huge_flop (the heaviest rows of a
+    // skewed matrix often share a block, which would walk them in turn)
     const int nlong = s_nlong;
-    for (int j = 0; j < nlong; ++j) {                  // uniform over the block
+    const int w = tid >> 6, ln = tid & 63;
+    for (int j = w; j < nlong; j += 4) {               // uniform over the wave
         const int t = s_long[j];
         const int b0 = rA[r0 + t], b1 = rA[r0 + t + 1];
+        if (b1 - b0 > FLOP_WAVE_ROW) {
+            if (ln == 0) huge[atomicAdd(&hdr->n_huge, 1u)] = r0 + t;
+            continue;
+        }
         unsigned long long g = 0;
-        for (int p = b0 + tid; p < b1; p += 256) g += edeg[p];
+#pragma unroll 4
+        for (int p = b0 + ln; p < b1; p += 64) g += entry_deg(p, cA, rB);
         g = wave_sum_u64(g);
-        if ((tid & 63) == 0 && g) atomicAdd(&s_f[t], g);
+        if (ln == 0) s_f[t] = g;                       // a long row's own lane left 0 there
     }
     __syncthreads();
-    if (tid < nr) {
-        f = s_f[tid];
-        flop_out[r0 + tid] = f > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)f;
-        const int b = sym_bin_l(f, ncolsB, L);
-        atomicAdd(&s_rows[b], 1ull);
-        atomicAdd(&s_flop[b], f);
-        atomicAdd(&s_nnza[b], (unsigned long long)(a1 - a0));
-        atomicAdd(&s_tot, f);
-        atomicMax(&s_max, f);
-    }
+    if (tid < nr && a1 - a0 <= FLOP_WAVE_ROW)
+        row_flop_put(r0 + tid, s_f[tid], a1 - a0, ncolsB, flop_out, s_rows, s_flop, s_nnza, &s_tot, &s_max, L);
     __syncthreads();
     if (tid < NSB && s_rows[tid]) {
         atomicAdd(&hdr->sym_rows[tid], s_rows[tid]);
@@ -131,6 +152,29 @@ __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restri
         atomicAdd(&hdr->total_flop, s_tot);
         atomicMax(&hdr->max_flop, s_max);
     }
+}
+
+// The listed rows of more than FLOP_WAVE_ROW entries, a block each (blocks
+// past the list's length leave at once), 2048 entries' loads in flight.
+__global__ __launch_bounds__(256) void k_huge_flop(const int32_t *__restrict__ rA, const int32_t *__restrict__ cA,
+                                                   const int32_t *__restrict__ rB, int64_t ncolsB,
+                                                   const int32_t *__restrict__ huge, uint32_t *__restrict__ flop_out,
+                                                   PlanHdr *hdr, BinLimits L) {
+    __shared__ unsigned long long s_g;
+    if (blockIdx.x >= hdr->n_huge) return;            // uniform over the block
+    const int row = huge[blockIdx.x];
+    const int b0 = rA[row], b1 = rA[row + 1];
+    if (threadIdx.x == 0) s_g = 0;
+    __syncthreads();
+    unsigned long long g = 0;
+#pragma unroll 8
+    for (int p = b0 + (int)threadIdx.x; p < b1; p += 256) g += entry_deg(p, cA, rB);
+    g = wave_sum_u64(g);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&s_g, g);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        row_flop_put(row, s_g, b1 - b0, ncolsB, flop_out, hdr->sym_rows, hdr->sym_flop, hdr->sym_nnza,
+                     &hdr->total_flop, &hdr->max_flop, L);
 }
 
 __global__ __launch_bounds__(256) void k_count_long_b(int n, const int32_t *__restrict__ rB, PlanHdr *hdr) {
@@ -431,8 +475,8 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
                     const u32x4 v = bm4[t * (Q_PER_CHUNK / 4) + ((j + t) & (Q_PER_CHUNK / 4 - 1))];
                     c += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
                 }
-                c += __shfl_xor(c, 1);
-                c += __shfl_xor(c, 2);
+                c += dpp_move<0xB1, 0xF>(c);          // quad lanes (1,0,3,2): xor 1
+                c += dpp_move<0x4E, 0xF>(c);          // quad lanes (2,3,0,1): xor 2
                 if ((t & 3) == 0) {
                     chunk_cnt[(size_t)slot * nchunks + chunk0 + t / 4] = (uint32_t)c;
                     atomicAdd(&s_total, c);
@@ -1368,7 +1412,7 @@ __global__ __launch_bounds__(64) void k_num_heap(const NumRow *__restrict__ rows
         end[t] = base + incl;
         soff[t * WAVE + ln] = cur[t];
         slo[t * WAVE + ln] = lo;
-        base += __shfl(incl, WAVE - 1);
+        base += wave_last(incl);
     }
     const int F = base;                         // <= HEAP_FCAP (the bin's rule)
     wave_sync();
@@ -1681,12 +1725,14 @@ hipError_t launch_validate(const CsrDev &a, int *err, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, uint32_t *edeg, PlanHdr *hdr,
+hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, int32_t *huge, PlanHdr *hdr,
                            const BinLimits &L, hipStream_t s) {
     if (A.nrows == 0) return hipSuccess;
-    if (A.nnz > 0)
-        k_entry_deg<<<(unsigned)std::min<int64_t>(grid1(A.nnz, 256), 8192), 256, 0, s>>>(A.nnz, A.cols, B.rpts, edeg);
-    k_row_flop<<<grid1(A.nrows, 256), 256, 0, s>>>((int)A.nrows, A.rpts, edeg, B.ncols, flop, hdr, L);
+    k_row_flop<<<grid1(A.nrows, 256), 256, 0, s>>>((int)A.nrows, A.rpts, A.cols, B.rpts, B.ncols, flop, huge, hdr,
+                                                    L);
+    const int64_t cap = A.nnz / (FLOP_WAVE_ROW + 1);   // rows that can be that long
+    if (cap > 0)
+        k_huge_flop<<<(unsigned)cap, 256, 0, s>>>(A.rpts, A.cols, B.rpts, B.ncols, huge, flop, hdr, L);
     return hipGetLastError();
 }
 

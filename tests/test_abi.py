@@ -83,7 +83,11 @@ def test_plan_scratch_bytes(lib):
     from paper_1804_01698_amd import binding as b
     arr = (b._Csr * 2)(b._Csr(1000, 10, 0, 1, None, None), b._Csr(0, 10, 0, 1, None, None))
     n = lib.spgemm_plan_scratch_bytes(2, arr)
-    assert n >= 1000 * 4 and n % 256 == 0
+    assert n >= 1000 * 4 and n % 256 == 0                 # header + row flop
+    arr2 = (b._Csr * 2)(b._Csr(1000, 10, 700, 1, None, None), b._Csr(0, 10, 0, 1, None, None))
+    assert lib.spgemm_plan_scratch_bytes(2, arr2) == n    # no row can exceed 4096 entries
+    arr3 = (b._Csr * 2)(b._Csr(1000, 10, 1 << 20, 1, None, None), b._Csr(0, 10, 0, 1, None, None))
+    assert lib.spgemm_plan_scratch_bytes(2, arr3) >= n + 4 * ((1 << 20) // 4097)   # list of long rows
     assert lib.spgemm_plan_scratch_bytes(0, arr) == 0
 
 
