@@ -312,12 +312,13 @@ int spgemm_stanza_read(const void *base, size_t nbytes, const int64_t *start, in
  * Many small independent products through one fixed sequence of launches per
  * batch, with no host synchronisation inside spgemm_batch_run (the sequence
  * can be captured in a HIP graph and replayed).  Every row of every product is
- * binned by its key bound min(row flop, ncols) (the row flop of Fig. 4) and
- * accumulated in one pass into an LDS hash table of the size the single
- * product path uses for that bound (Section 4.2.1); its entries are staged in
- * a bound-sized slot of a caller-provided arena and then compacted into CSR
- * inside the arena: the one-phase scheme of Section 2 (allocate an upper
- * bound, then compact).  A product with a row whose key bound exceeds 8448 is
+ * binned by its key bound min(row flop, ncols) (the row flop of Fig. 4) into
+ * the LDS hash table size the single-product path uses for that bound
+ * (Section 4.2.1), and the two phases of Section 2 run on the device for the
+ * whole batch: the rows' distinct columns are counted, the counts scanned into
+ * places, and every row accumulated and written at its place in a
+ * caller-provided arena sized from the bounds (an upper bound of nnz(C)).  A
+ * product with a row whose key bound exceeds 8448 is
  * outside the batched range: none of its rows is computed and it gets status
  * SPGEMM_ERR_UNSUPPORTED (use the plan path for it).  Operands must be valid
  * CSR (see spgemm_csr); the batch path does not validate them.  The total row
@@ -345,8 +346,8 @@ size_t spgemm_batch_scratch_bytes(int nprod, const spgemm_csr *A);
 int spgemm_batch_prepare(int nprod, const spgemm_csr *A, const spgemm_csr *B, const unsigned *flags,
                          void *scratch, hipStream_t stream);
 
-/* Analyse a prepared batch: the row flop of every row (Fig. 4), its bin and
- * its staging slot, kept in scratch for every later run; per product, into
+/* Analyse a prepared batch: the row flop of every row (Fig. 4) and its bin,
+ * kept in scratch for every later run; per product, into
  * host arrays of nprod: flop[p] (multiplications), bound[p] (sum over the
  * product's batched rows of min(row flop, ncols): an upper bound of
  * nnz(C[p])) and, if max_key is not NULL, max_key[p] (largest
@@ -365,7 +366,7 @@ enum { SPGEMM_BATCH_BINS = 11 };
 int spgemm_batch_bin_rows(int nprod, const spgemm_csr *A, void *scratch, int64_t *rows, hipStream_t stream);
 
 /* Arena bytes for a batch with the given per-product bounds (host array):
- * 24 bytes per bounded entry plus 8 per row pointer, 256-byte aligned parts. */
+ * 12 bytes per bounded entry plus 8 per row pointer, 256-byte aligned parts. */
 size_t spgemm_batch_arena_bytes(int nprod, const spgemm_csr *A, const int64_t *bound);
 
 /* Run a prepared batch: every product C[p] = A[p]*B[p] lands in the arena;

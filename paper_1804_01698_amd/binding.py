@@ -366,7 +366,7 @@ BATCH_XMAX = 8448          # rows above this key bound are outside the batched r
 class Batch:
     """Many small products C[p] = A[p] @ B[p] through one fixed sequence of
     launches (spgemm_batch_*).  Construction uploads the batch and analyses it
-    (row flop, bins, staging offsets; synchronises the stream) and, unless
+    (row flop and bins; synchronises the stream) and, unless
     ``allocate=False``, allocates the arena (``arena_bytes``).  ``run()``
     enqueues kernels only (capturable in a HIP graph); ``outputs()`` reads the
     per-product results back and returns views into the arena."""

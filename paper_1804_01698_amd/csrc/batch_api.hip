@@ -18,7 +18,7 @@ inline size_t al(size_t x) { return (x + BA - 1) & ~(BA - 1); }
 // Scratch: batch description, counters and per-row arrays.
 struct ScratchLayout {
     size_t descs, pflop, pbound, pmax, pstatus, err, bcnt, bcur, boff;
-    size_t pid, bin, kx, a0, a1, list, nnz, soff, gpos, bsum, total;
+    size_t pid, bin, kx, a0, a1, list, nnz, gpos, bsum, total;
 };
 
 ScratchLayout scratch_layout(int nprod, int64_t mtot) {
@@ -41,23 +41,21 @@ ScratchLayout scratch_layout(int nprod, int64_t mtot) {
     L.a1 = o; o += al(4 * m);
     L.list = o; o += al(16 * m);
     L.nnz = o; o += al(4 * m);
-    L.soff = o; o += al(8 * m);
     L.gpos = o; o += al(8 * m);
     L.bsum = o; o += al(8 * ((m + 4095) / 4096 + 2));
     L.total = o;
     return L;
 }
 
-// Arena: staging slots, then the products' CSR arrays (K = sum of key bounds).
+// Arena: the products' CSR arrays (K = sum of key bounds, an upper bound of
+// the entries).
 struct ArenaLayout {
-    size_t scols, svals, orpts, ocols, ovals, total;
+    size_t orpts, ocols, ovals, total;
 };
 
 ArenaLayout arena_layout(int nprod, int64_t mtot, int64_t K) {
     ArenaLayout L{};
     size_t o = 0;
-    L.scols = o; o += al(4 * (size_t)K);
-    L.svals = o; o += al(8 * (size_t)K);
     L.orpts = o; o += al(8 * (size_t)(mtot + nprod));
     L.ocols = o; o += al(4 * (size_t)K);
     L.ovals = o; o += al(8 * (size_t)K);
@@ -152,8 +150,8 @@ int spgemm_batch_analyse(int nprod, const spgemm_csr *A, void *scratch, int64_t 
     const ScratchLayout L = scratch_layout(nprod, mtot);
     char *s = (char *)scratch;
     const Views v = views(s, L);
-    hipError_t e = launch_batch_analyse(v.d, nprod, mtot, v.r, v.c, (int4 *)(s + L.list), (long long *)(s + L.bsum),
-                                        (int64_t *)(s + L.soff), (uint32_t *)(s + L.nnz), stream);
+    hipError_t e = launch_batch_analyse(v.d, nprod, mtot, v.r, v.c, (int4 *)(s + L.list), (uint32_t *)(s + L.nnz),
+                                        stream);
     if (e != hipSuccess) return SPGEMM_ERR_HIP;
     std::vector<unsigned long long> h(3 * (size_t)nprod);
     // pflop, pbound and pmax are laid out one after another (each 256-aligned)
@@ -217,11 +215,8 @@ int spgemm_batch_run(int nprod, const spgemm_csr *A, spgemm_dtype dtype, const i
     BatchBufs w;
     w.list = (int4 *)(s + L.list);
     w.bsum = (long long *)(s + L.bsum);
-    w.soff = (int64_t *)(s + L.soff);
     w.gpos = (int64_t *)(s + L.gpos);
     w.nnz = (uint32_t *)(s + L.nnz);
-    w.scols = (int32_t *)(a + R.scols);
-    w.svals = a + R.svals;
     w.K = K;
     w.ocols = (int32_t *)(a + R.ocols);
     w.ovals = a + R.ovals;

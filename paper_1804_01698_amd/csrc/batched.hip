@@ -5,12 +5,14 @@
 // Rows of all products form one global row space (product p owns rows
 // [row_off[p], row_off[p+1])).  Every row is put in a bin by its key bound
 // x = min(row flop, ncols) (Fig. 4's row flop, capped by the width of C), with
-// the same table sizes as the single-product path, and a persistent kernel per
-// bin accumulates each of its rows in one pass into an LDS hash table of keys
-// and values.  The entries are compacted (and sorted when the product asks for
-// it) into an x-sized staging slot; the row counts are then scanned and every
-// row copied to its final place.  This is the one-phase variant of Section 2
-// (allocate an upper bound, then compact) applied to a batch.
+// the same table sizes as the single-product path.  The two phases of Section
+// 2 then run on the device for the whole batch: a persistent kernel per bin
+// counts each row's distinct columns in a keys-only LDS table, one scan of the
+// counts gives every row its place in C, and a persistent kernel per bin
+// accumulates each row in an LDS table of keys and values and writes it there
+// (sorted when its product asks for it).  The caller sizes the arena from the
+// bounds x (an upper bound of nnz(C)) before the run, so the run itself
+// allocates nothing and needs no host round trip.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -203,28 +205,70 @@ __global__ __launch_bounds__(1024) void k_bat_scan_down(const uint32_t *__restri
     }
 }
 
-// The rows of one bin, a block of G threads per row (persistent over the
-// bin's list): one pass accumulates keys and values into a T-slot LDS table,
-// the occupied slots are compacted (sorted when the product asks for it) and
-// written to the row's staging slot.
-template <int G, int T, int U, typename V>
-__global__ __launch_bounds__(G) void k_bat_hash(const BatchDesc *__restrict__ d, int bin, BatchRows r,
-                                                BatchCounters c, const int4 *__restrict__ list,
-                                                const int64_t *__restrict__ soff, int64_t cap_total,
-                                                int32_t *__restrict__ scols, V *__restrict__ svals,
-                                                uint32_t *__restrict__ nnz) {
+// Symbolic phase of one bin, a block of G threads per row (persistent over
+// the bin's list): the row's distinct columns are counted in a keys-only LDS
+// hash table of T slots (Section 4.2.1), as in the single-product path.
+template <int G, int T, int U>
+__global__ __launch_bounds__(G) void k_bat_sym(const BatchDesc *__restrict__ d, int bin, BatchCounters c,
+                                               const int4 *__restrict__ list, uint32_t *__restrict__ nnz) {
     __shared__ __align__(16) int keys[T];
-    __shared__ V vals[T];
-    __shared__ SegLds<G, true, V> sg;
+    __shared__ SegLds<G, false, double> sg;
     const int tid = threadIdx.x;
     const unsigned n = c.bcur[bin];             // rows actually listed
     const int4 *lst = list + c.boff[bin];
     int ovf = 0;
     for (unsigned it = blockIdx.x; it < n; it += gridDim.x) {
         const int4 rec = lst[it];                 // row, product, A range
+        const BatchDesc &q = d[rec.y];
+        table_clear<G, T, false, double>(keys, nullptr);
+        __syncthreads();
+        int cnt = 0;
+        enum_row<G, U, false, double>(
+            rec.z, rec.w, q.cA, nullptr, sg,
+            [&](int k, int &lo, int &hi) { lo = q.rB[k]; hi = q.rB[k + 1]; },
+            [&](const int (&qq)[U], const bool (&ok)[U], const double (&)[U]) {
+                int col[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int cb = q.cB[qq[u]];           // qq is always a valid index
+                    col[u] = ok[u] ? cb : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) cnt += bkt_insert<false, double, 1>(keys, nullptr, T, col[u], 0.0, ovf);
+            });
+        __syncthreads();
+        int total;
+        block_excl_scan<G, int>(cnt, total, sg.wsum);
+        if (tid == 0) nnz[rec.x] = (uint32_t)total;
+        __syncthreads();
+    }
+    if (ovf) atomicOr(c.err, (unsigned)ERR_PROBE);
+}
+
+// Numeric phase of one bin: the row is accumulated into an LDS table of keys
+// and values and leaves the table straight for its place in C (gpos, the scan
+// of the symbolic counts), sorted when its product asks for it.  A row whose
+// place runs past the arena's capacity of cap_total entries (operands changed
+// since the arena was sized) is not written and flags an error.
+template <int G, int T, int U, typename V>
+__global__ __launch_bounds__(G) void k_bat_num(const BatchDesc *__restrict__ d, int bin, BatchCounters c,
+                                               const int4 *__restrict__ list, const uint32_t *__restrict__ nnz,
+                                               const int64_t *__restrict__ gpos, int64_t cap_total,
+                                               int32_t *__restrict__ ocols, V *__restrict__ ovals) {
+    __shared__ __align__(16) int keys[T];
+    __shared__ __align__(16) V vals[T];
+    __shared__ SegLds<G, true, V> sg;
+    const unsigned n = c.bcur[bin];
+    const int4 *lst = list + c.boff[bin];
+    int ovf = 0;
+    for (unsigned it = blockIdx.x; it < n; it += gridDim.x) {
+        const int4 rec = lst[it];
         const int64_t g = rec.x;
         const BatchDesc &q = d[rec.y];
-        for (int s = tid; s < T; s += G) { keys[s] = -1; vals[s] = V(0); }
+        const int64_t o = gpos[g];
+        const int cnt = (int)nnz[g];
+        table_clear<G, T, true, V>(keys, vals);
         __syncthreads();
         const V *vB = (const V *)q.vB;
         enum_row<G, U, true, V>(
@@ -235,89 +279,24 @@ __global__ __launch_bounds__(G) void k_bat_hash(const BatchDesc *__restrict__ d,
                 V xv[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int c = q.cB[qq[u]];             // qq is always a valid index
+                    const int cb = q.cB[qq[u]];           // qq is always a valid index
                     const V b = vB[qq[u]];
-                    col[u] = ok[u] ? c : 0;
+                    col[u] = ok[u] ? cb : 0;
                     xv[u] = ok[u] ? av[u] * b : V(0);
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (ok[u]) bkt_insert<true, V>(keys, vals, T, col[u], xv[u], ovf);
+                    if (ok[u]) bkt_insert<true, V, 1>(keys, vals, T, col[u], xv[u], ovf);
             });
         __syncthreads();
-        constexpr int S = (T + G - 1) / G;
-        int kk[S];
-        V vv[S];
-        int cnt = 0;
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int s = tid * S + j;
-            kk[j] = -1;
-            vv[j] = V(0);
-            if (s < T) { kk[j] = keys[s]; vv[j] = vals[s]; }
-            cnt += kk[j] != -1;
-        }
-        int total;
-        int pos = block_excl_scan<G, int>(cnt, total, sg.wsum);
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < S; ++j)
-            if (kk[j] != -1) { keys[pos] = kk[j]; vals[pos] = vv[j]; ++pos; }
-        __syncthreads();
-        if (q.flags & 1u) bitonic_sort_lds<G, V>(keys, vals, total);
-        const int64_t o = soff[g];
-        // the slot holds x >= nnz entries; a slot past the arena's staging
-        // capacity (operands changed since the arena was sized) stays empty
-        const int cap = o + (int64_t)r.kx[g] <= cap_total ? (int)r.kx[g] : 0;
-        const int m = total <= cap ? total : cap;
-        for (int j = tid; j < m; j += G) {
-            scols[o + j] = keys[j];
-            svals[o + j] = vals[j];
-        }
-        if (tid == 0) {
-            nnz[g] = (uint32_t)m;
-            if (total > cap) atomicOr(c.err, (unsigned)ERR_COUNT);
-        }
+        const int expected = o + cnt <= cap_total ? cnt : 0;
+        if (q.flags & 1u)
+            compact_store<G, T, true, V>(keys, vals, sg.wsum, o, expected, ocols, ovals, (int *)c.err);
+        else
+            compact_store_unsorted<G, T, V>(keys, vals, sg.wsum, o, expected, ocols, ovals, (int *)c.err);
         __syncthreads();
     }
     if (ovf) atomicOr(c.err, (unsigned)ERR_PROBE);
-}
-
-// Rows move from their staging slots to the batch's CSR arrays, a wave per
-// 64 consecutive rows: their output is one contiguous range, which the wave
-// writes element by element (each lane finds its element's row by bisection
-// over the rows' exclusive prefix counts in LDS).
-template <typename V>
-__global__ __launch_bounds__(256) void k_bat_copy(int64_t mtot, const int64_t *__restrict__ soff,
-                                                  const int64_t *__restrict__ gpos,
-                                                  const uint32_t *__restrict__ nnz,
-                                                  const int32_t *__restrict__ scols, const V *__restrict__ svals,
-                                                  int32_t *__restrict__ ocols, V *__restrict__ ovals) {
-    __shared__ int s_pre[4][64];
-    __shared__ int64_t s_src[4][64];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t g0 = ((int64_t)blockIdx.x * 4 + w) * 64; g0 < mtot; g0 += nw * 64) {
-        const int64_t g = g0 + lane;
-        const int n = g < mtot ? (int)nnz[g] : 0;
-        const int incl = wave_incl_scan<int>(n);
-        const int total = __shfl(incl, 63);
-        s_pre[w][lane] = incl - n;
-        s_src[w][lane] = g < mtot ? soff[g] : 0;
-        const int64_t o0 = gpos[g0];
-        wave_sync();
-        for (int t = lane; t < total; t += 64) {
-            int lo = 0, hi = 63;                  // last row with prefix <= t
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_pre[w][mid] <= t) lo = mid; else hi = mid - 1;
-            }
-            const int64_t src = s_src[w][lo] + (t - s_pre[w][lo]);
-            __builtin_nontemporal_store(scols[src], &ocols[o0 + t]);
-            __builtin_nontemporal_store(svals[src], &ovals[o0 + t]);
-        }
-        wave_sync();
-    }
 }
 
 // Per-product row pointers (relative to the product's first entry).  Slots:
@@ -382,19 +361,28 @@ static int occupancy(K kern, int G) {
     return occ;
 }
 
-template <int G, int T, typename V>
-static void bin_launch(int b, const BatchDesc *d, int64_t mtot, const BatchRows &r, const BatchCounters &c,
-                       const int4 *list, const int64_t *soff, int64_t cap_total, int32_t *scols, V *svals,
+// Symbolic and numeric launches of bin b (persistent grids over the bin's
+// list; a block of an empty or short list leaves at once).
+template <int G, int T>
+static void sym_launch(int b, const BatchDesc *d, int64_t mtot, const BatchCounters &c, const int4 *list,
                        uint32_t *nnz, hipStream_t s, int ncu) {
-    constexpr int U = u_for(G, T / 2 + 1) < 4 ? u_for(G, T / 2 + 1) : 4;
-    static const int occ = occupancy(k_bat_hash<G, T, U, V>, G);
+    constexpr int U = u_for(G, T / 2) < 4 ? u_for(G, T / 2) : 4;
+    static const int occ = occupancy(k_bat_sym<G, T, U>, G);
     const unsigned grid = (unsigned)std::min<int64_t>(mtot, (int64_t)ncu * occ);
-    k_bat_hash<G, T, U, V><<<grid, G, 0, s>>>(d, b, r, c, list, soff, cap_total, scols, svals, nnz);
+    k_bat_sym<G, T, U><<<grid, G, 0, s>>>(d, b, c, list, nnz);
+}
+
+template <int G, int T, typename V>
+static void num_launch(int b, const BatchDesc *d, int64_t mtot, const BatchCounters &c, const BatchBufs &w,
+                       hipStream_t s, int ncu) {
+    constexpr int U = u_for(G, T / 2 + 1) < 4 ? u_for(G, T / 2 + 1) : 4;
+    static const int occ = occupancy(k_bat_num<G, T, U, V>, G);
+    const unsigned grid = (unsigned)std::min<int64_t>(mtot, (int64_t)ncu * occ);
+    k_bat_num<G, T, U, V><<<grid, G, 0, s>>>(d, b, c, w.list, w.nnz, w.gpos, w.K, w.ocols, (V *)w.ovals);
 }
 
 hipError_t launch_batch_analyse(const BatchDesc *d, int nprod, int64_t mtot, const BatchRows &r,
-                                const BatchCounters &c, int4 *list, long long *bsum, int64_t *soff,
-                                uint32_t *nnz, hipStream_t s) {
+                                const BatchCounters &c, int4 *list, uint32_t *nnz, hipStream_t s) {
     k_bat_zero<<<g256(std::max(nprod, BAT_NB)), 256, 0, s>>>(c, nprod);
     if (mtot > 0) {
         const unsigned g = (unsigned)std::min<int64_t>((mtot + 31) / 32, 8192);
@@ -402,28 +390,34 @@ hipError_t launch_batch_analyse(const BatchDesc *d, int nprod, int64_t mtot, con
         k_bat_binscan<<<1, 64, 0, s>>>(c);
         k_bat_scatter<<<g256(mtot), 256, 0, s>>>(mtot, r, c, list, nnz);
     }
-    // also sets the scan total (0 for a batch without rows) that the run reads
-    return scan_u32(r.kx, mtot, bsum, soff, s);
+    return hipGetLastError();
 }
 
+// Two phases on the device: every bin's symbolic counts, one scan of the
+// counts into places in C, then every bin's numeric rows written in place.
 template <typename V>
-static hipError_t batch_rows_t(const BatchDesc *d, int64_t mtot, const BatchRows &r, const BatchCounters &c,
-                               const BatchBufs &w, hipStream_t s, int ncu) {
-    V *sv = (V *)w.svals;
-    bin_launch<NUM_G[1], NUM_T[1], V>(1, d, mtot, r, c, w.list, w.soff, w.K, w.scols, sv, w.nnz, s, ncu);
-    bin_launch<NUM_G[2], NUM_T[2], V>(2, d, mtot, r, c, w.list, w.soff, w.K, w.scols, sv, w.nnz, s, ncu);
-    bin_launch<NUM_G[3], NUM_T[3], V>(3, d, mtot, r, c, w.list, w.soff, w.K, w.scols, sv, w.nnz, s, ncu);
-    bin_launch<NUM_G[4], NUM_T[4], V>(4, d, mtot, r, c, w.list, w.soff, w.K, w.scols, sv, w.nnz, s, ncu);
-    bin_launch<NUM_G[5], NUM_T[5], V>(5, d, mtot, r, c, w.list, w.soff, w.K, w.scols, sv, w.nnz, s, ncu);
-    bin_launch<NUM_G[6], NUM_T[6], V>(6, d, mtot, r, c, w.list, w.soff, w.K, w.scols, sv, w.nnz, s, ncu);
-    bin_launch<NUM_G[7], NUM_T[7], V>(7, d, mtot, r, c, w.list, w.soff, w.K, w.scols, sv, w.nnz, s, ncu);
-    bin_launch<NUM_G[8], NUM_T[8], V>(8, d, mtot, r, c, w.list, w.soff, w.K, w.scols, sv, w.nnz, s, ncu);
-    bin_launch<NUM_G[9], NUM_T[9], V>(9, d, mtot, r, c, w.list, w.soff, w.K, w.scols, sv, w.nnz, s, ncu);
+static hipError_t batch_rows_t(const BatchDesc *d, int64_t mtot, const BatchCounters &c, const BatchBufs &w,
+                               hipStream_t s, int ncu) {
+    sym_launch<SYM_G[1], SYM_T[1]>(1, d, mtot, c, w.list, w.nnz, s, ncu);
+    sym_launch<SYM_G[2], SYM_T[2]>(2, d, mtot, c, w.list, w.nnz, s, ncu);
+    sym_launch<SYM_G[3], SYM_T[3]>(3, d, mtot, c, w.list, w.nnz, s, ncu);
+    sym_launch<SYM_G[4], SYM_T[4]>(4, d, mtot, c, w.list, w.nnz, s, ncu);
+    sym_launch<SYM_G[5], SYM_T[5]>(5, d, mtot, c, w.list, w.nnz, s, ncu);
+    sym_launch<SYM_G[6], SYM_T[6]>(6, d, mtot, c, w.list, w.nnz, s, ncu);
+    sym_launch<SYM_G[7], SYM_T[7]>(7, d, mtot, c, w.list, w.nnz, s, ncu);
+    sym_launch<SYM_G[8], SYM_T[8]>(8, d, mtot, c, w.list, w.nnz, s, ncu);
+    sym_launch<SYM_G[9], SYM_T[9]>(9, d, mtot, c, w.list, w.nnz, s, ncu);
     hipError_t e = scan_u32(w.nnz, mtot, w.bsum, w.gpos, s);
     if (e != hipSuccess) return e;
-    const unsigned gc = (unsigned)std::min<int64_t>((mtot + 255) / 256, 16384);
-    k_bat_copy<V><<<gc, 256, 0, s>>>(mtot, w.soff, w.gpos, w.nnz, w.scols, (const V *)w.svals, w.ocols,
-                                     (V *)w.ovals);
+    num_launch<NUM_G[1], NUM_T[1], V>(1, d, mtot, c, w, s, ncu);
+    num_launch<NUM_G[2], NUM_T[2], V>(2, d, mtot, c, w, s, ncu);
+    num_launch<NUM_G[3], NUM_T[3], V>(3, d, mtot, c, w, s, ncu);
+    num_launch<NUM_G[4], NUM_T[4], V>(4, d, mtot, c, w, s, ncu);
+    num_launch<NUM_G[5], NUM_T[5], V>(5, d, mtot, c, w, s, ncu);
+    num_launch<NUM_G[6], NUM_T[6], V>(6, d, mtot, c, w, s, ncu);
+    num_launch<NUM_G[7], NUM_T[7], V>(7, d, mtot, c, w, s, ncu);
+    num_launch<NUM_G[8], NUM_T[8], V>(8, d, mtot, c, w, s, ncu);
+    num_launch<NUM_G[9], NUM_T[9], V>(9, d, mtot, c, w, s, ncu);
     return hipGetLastError();
 }
 
@@ -432,8 +426,11 @@ hipError_t launch_batch_run(int dtype, const BatchDesc *d, int nprod, int64_t mt
                             int ncu) {
     k_bat_reset_err<<<1, 64, 0, s>>>(c.err);
     if (mtot > 0) {
-        const hipError_t e = dtype == SPGEMM_F64 ? batch_rows_t<double>(d, mtot, r, c, w, s, ncu)
-                                                 : batch_rows_t<unsigned long long>(d, mtot, r, c, w, s, ncu);
+        const hipError_t e = dtype == SPGEMM_F64 ? batch_rows_t<double>(d, mtot, c, w, s, ncu)
+                                                 : batch_rows_t<unsigned long long>(d, mtot, c, w, s, ncu);
+        if (e != hipSuccess) return e;
+    } else {
+        const hipError_t e = scan_u32(w.nnz, 0, w.bsum, w.gpos, s);   // sets the total (0) the results read
         if (e != hipSuccess) return e;
     }
     // the total entry count is the scan total bsum[nb], read on the device

@@ -33,7 +33,7 @@ struct BatchDesc {
 struct BatchRows {
     int32_t *pid;          // product of the row
     uint8_t *bin;          // bin of the row
-    uint32_t *kx;          // staging slot size: min(flop, ncols) for batched rows, else 0
+    uint32_t *kx;          // key bound: min(flop, ncols) for batched rows, else 0
     int32_t *a0, *a1;      // the row's entries of A: [a0, a1)
 };
 
@@ -49,23 +49,20 @@ struct BatchCounters {
 struct BatchBufs {
     int4 *list;            // rows by bin: {row, product, a0, a1}
     long long *bsum;       // scan block sums (+ total)
-    int64_t *soff;         // staging offset per row
     int64_t *gpos;         // output offset per row
-    uint32_t *nnz;         // row counts
-    int32_t *scols;        // staging: K entries
-    void *svals;
-    int64_t K;
+    uint32_t *nnz;         // row counts (symbolic phase)
+    int64_t K;             // output capacity (entries): the sum of the bounds
     int32_t *ocols;
     void *ovals;
     int64_t *orpts;
     int64_t rpts_base, cols_base, vals_base;   // byte offsets of the outputs in the arena
 };
 
-// Row flop, bins, bin lists and staging offsets (once per batch structure).
+// Row flop, bins and bin lists (once per batch structure).
 hipError_t launch_batch_analyse(const BatchDesc *d, int nprod, int64_t mtot, const BatchRows &r,
-                                const BatchCounters &c, int4 *list, long long *bsum, int64_t *soff,
-                                uint32_t *nnz, hipStream_t s);
-// Accumulation, compaction and results (every run; kernels only).
+                                const BatchCounters &c, int4 *list, uint32_t *nnz, hipStream_t s);
+// Symbolic counts, their scan, numeric rows in place and results (every run;
+// kernels only).
 hipError_t launch_batch_run(int dtype, const BatchDesc *d, int nprod, int64_t mtot, const BatchRows &r,
                             const BatchCounters &c, const BatchBufs &w, spgemm_batch_result *res, hipStream_t s,
                             int ncu);
