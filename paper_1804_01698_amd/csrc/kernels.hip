@@ -318,7 +318,7 @@ __device__ __forceinline__ RowPre<V> row_pre(int row, int a0, int a1, const int3
 // ----------------------------------------------------------------------- symbolic
 
 template <int G, int T, int U, bool PERSIST>
-__global__ __launch_bounds__(G) __attribute__((amdgpu_waves_per_eu(G == 1024 ? 8 : 1))) void k_sym_hash(const int32_t *__restrict__ perm, const int2 *__restrict__ prow,
+__global__ __launch_bounds__(G) __attribute__((amdgpu_waves_per_eu(8))) void k_sym_hash(const int32_t *__restrict__ perm, const int2 *__restrict__ prow,
                                                 int64_t perm_off, unsigned nrows,
                                                 const int32_t *__restrict__ cA,
                                                 const int32_t *__restrict__ rB,
@@ -1747,9 +1747,9 @@ hipError_t launch_sym_scatter(int m, const uint32_t *flop, const int32_t *rA, in
 template <int G, int T>
 static void sym_hash_l(unsigned nrows, const int32_t *perm, const int2 *prow, int64_t off, const CsrDev &A,
                        const CsrDev &B, int32_t *nnz_row, WsHdr *wh, HashCfg hc, int ncu, hipStream_t s) {
-    // 1024-thread bins: four products per lane keep the kernel within the 64
-    // registers that two blocks per CU leave
-    constexpr int U = G == 1024 ? 4 : u_for(G, T / 2 + 1);
+    // at most four products per lane keep the kernel within 64 registers
+    // (eight waves per SIMD: two 1024-thread blocks per CU)
+    constexpr int U = u_for(G, T / 2 + 1) < 4 ? u_for(G, T / 2 + 1) : 4;
     // wide bins (few blocks per CU) run persistent; narrow ones a block per row
     constexpr bool P = G >= 512;
     static const int occ = P ? blocks_per_cu(k_sym_hash<G, T, U, P>, G) : 0;
