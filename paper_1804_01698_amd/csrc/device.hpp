@@ -438,7 +438,104 @@ __device__ void bitonic_sort_lds(int *keys, V *vals, int n) {
     }
 }
 
-// Compact the occupied slots of an LDS table to its front (table order),
+// Sort the n <= T entries at the front of a T-slot table (distinct keys >= 0)
+// in one pass of bucketing: keys are spread over NB = T/2 buckets by their
+// place in [min, max] (a monotone map), the bucket counts are scanned, every
+// entry is scattered to its bucket, and its rank is its bucket's start plus
+// the number of smaller keys in the bucket (a handful on average).  The
+// entries wait in registers meanwhile, and the value array serves as the
+// counters.  A few LDS operations per entry, against the two LDS round trips
+// per stage of a bitonic network or the n comparisons per entry of a rank
+// count.  Ends with the sorted entries at [0, n) and a block barrier.
+template <int G, int T, typename V>
+__device__ void bucket_sort_lds(int *keys, V *vals, int n) {
+    static_assert(T % G == 0 && sizeof(V) == 8, "table layout");
+    constexpr int E = T / G;                  // entries per thread at most
+    constexpr int NB = T / 2;
+    constexpr int NW = G / WAVE;
+    static_assert(3 * NB + 2 * NW <= 2 * T, "counters fit the value array");
+    if (n <= 1) return;                       // uniform over the block
+    const int tid = threadIdx.x;
+    int k[E], b[E];
+    V v[E];
+    int lo = INT32_MAX, hi = -1;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int e = tid + i * G;
+        k[i] = e < n ? keys[e] : -1;
+        v[i] = e < n ? vals[e] : V(0);
+        if (e < n) { lo = min(lo, k[i]); hi = max(hi, k[i]); }
+    }
+    lo = __ockl_wfred_min_i32(lo);
+    hi = __ockl_wfred_max_i32(hi);
+    block_sync<G>();                          // every entry read: the arrays are free
+    int *cnt = reinterpret_cast<int *>(vals);
+    int *start = cnt + NB;
+    int *cur = start + NB;
+    if constexpr (NW > 1) {
+        int *red = cur + NB;                  // per-wave minima, then maxima
+        if ((tid & 63) == 0) { red[tid >> 6] = lo; red[NW + (tid >> 6)] = hi; }
+    }
+    for (int i = tid; i < NB; i += G) { cnt[i] = 0; cur[i] = 0; }
+    block_sync<G>();
+    if constexpr (NW > 1) {
+        const int *red = cur + NB;
+        for (int w = 0; w < NW; ++w) { lo = min(lo, red[w]); hi = max(hi, red[NW + w]); }
+    }
+    // bucket of key x: x - lo when the keys span at most NB values, else
+    // (x - lo) * m / 2^32 with m = floor(NB * 2^32 / span): monotone in x, < NB
+    const unsigned span = (unsigned)(hi - lo) + 1u;
+    const unsigned long long m = span <= (unsigned)NB ? 0ull : ((unsigned long long)NB << 32) / span;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const unsigned x = (unsigned)(k[i] - lo);
+        b[i] = k[i] < 0 ? 0 : (m == 0 ? (int)x : (int)(((unsigned long long)x * m) >> 32));
+        if (k[i] >= 0) atomicAdd(&cnt[b[i]], 1);
+    }
+    block_sync<G>();
+    {
+        // exclusive scan of the counts: NB/G consecutive buckets per thread
+        constexpr int PB = (NB + G - 1) / G;
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            const int q = tid * PB + j;
+            if (q < NB) c += cnt[q];
+        }
+        int tot;
+        int pre = block_excl_scan<G, int>(c, tot, reinterpret_cast<int *>(keys) + T - (NW + 1));
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            const int q = tid * PB + j;
+            if (q < NB) { start[q] = pre; pre += cnt[q]; }
+        }
+    }
+    block_sync<G>();
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+        if (k[i] >= 0) keys[start[b[i]] + atomicAdd(&cur[b[i]], 1)] = k[i];
+    block_sync<G>();
+    int r[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        r[i] = -1;
+        if (k[i] >= 0) {
+            const int s0 = start[b[i]], s1 = s0 + cnt[b[i]];
+            int c = s0;
+            for (int q = s0; q < s1; ++q) c += keys[q] < k[i];
+            r[i] = c;
+        }
+    }
+    block_sync<G>();                          // every bucket read before the entries move
+    int *kk = keys;
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+        if (r[i] >= 0) { kk[r[i]] = k[i]; vals[r[i]] = v[i]; }
+    block_sync<G>();
+}
+
+// Compact the occupied slots of an LDS table to its front (slots read lane by
+// lane, so in a permuted table order; the sorted output does not see it),
 // optionally sort them, and copy them to the output.  Returns the count.
 template <int G, int T, bool SORTED, typename V>
 __device__ __forceinline__ int compact_store(int *keys, V *vals, int *wsum, int64_t out_pos,
@@ -451,7 +548,7 @@ __device__ __forceinline__ int compact_store(int *keys, V *vals, int *wsum, int6
     int c = 0;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-        const int s = tid * S + j;
+        const int s = j * G + tid;                    // lane by lane: no bank conflicts
         kk[j] = -1;
         vv[j] = V(0);
         if (s < T) { kk[j] = keys[s]; vv[j] = vals[s]; }
@@ -464,9 +561,12 @@ __device__ __forceinline__ int compact_store(int *keys, V *vals, int *wsum, int6
     for (int j = 0; j < S; ++j)
         if (kk[j] != -1) { keys[pos] = kk[j]; vals[pos] = vv[j]; ++pos; }
     block_sync<G>();
-    if constexpr (SORTED) bitonic_sort_lds<G, V>(keys, vals, total);
     const int n = total < expected ? total : expected;
     if (total != expected && tid == 0) atomicOr(err, ERR_COUNT);
+    if constexpr (SORTED) {
+        if constexpr (G < 512) bucket_sort_lds<G, T, V>(keys, vals, total);
+        else bitonic_sort_lds<G, V>(keys, vals, total);
+    }
     for (int j = tid; j < n; j += G) {
         __builtin_nontemporal_store(keys[j], &colsC[out_pos + j]);
         __builtin_nontemporal_store(vals[j], &valsC[out_pos + j]);

@@ -961,15 +961,26 @@ __global__ __launch_bounds__(G) void k_num_hash(const NumRow *__restrict__ rows,
             // Sorted output of a wide bin by rank instead of a bitonic sort: the
             // columns of C are swept in passes of as many columns as a bitmap in
             // the (now idle) enumeration LDS holds; in a pass, the keys inside
-            // it set their bit, an exclusive popcount prefix per word plus the
-            // keys of the earlier passes gives each its rank, and every entry
-            // goes straight to its place.  Up to rank_passes(T) passes; wider
+            // it set their bit, and an exclusive popcount prefix per word plus
+            // the keys of the earlier passes gives each its rank.  Each thread
+            // holds its slots (lane by lane) in registers through the passes;
+            // the entries then move to their ranks inside the table and leave
+            // in coalesced runs (stores straight to scattered places of C cost
+            // partial-line writes to HBM).  Up to rank_passes(T) passes; wider
             // matrices sort by bitonic networks.
             constexpr int RW = (int)(sizeof(NumLds<G, V>) / sizeof(uint2));
             constexpr int64_t PW = (int64_t)RW * 32;
+            constexpr int SL = T / G;                             // slots per thread
+            static_assert(T % G == 0, "table size a multiple of the block");
             const int npass = (int)((ncolsB + PW - 1) / PW);
             if (npass <= rank_passes(T)) {
                 uint2 *rw = reinterpret_cast<uint2 *>(&lds);
+                int kr[SL], rk[SL];
+#pragma unroll
+                for (int j = 0; j < SL; ++j) {
+                    kr[j] = keys[j * G + tid];
+                    rk[j] = -1;
+                }
                 int base = 0;
                 for (int ps = 0; ps < npass; ++ps) {
                     const int c0 = (int)(ps * PW);
@@ -977,10 +988,10 @@ __global__ __launch_bounds__(G) void k_num_hash(const NumRow *__restrict__ rows,
                     const int nw = (int)((span + 31) >> 5);
                     for (int i = tid; i < nw; i += G) rw[i] = make_uint2(0u, 0u);
                     __syncthreads();
-                    for (int s = tid; s < T; s += G) {
-                        const int k = keys[s];
-                        const uint32_t off = (uint32_t)(k - c0);
-                        if (k != -1 && off < (uint32_t)span) atomicOr(&rw[off >> 5].x, 1u << (off & 31));
+#pragma unroll
+                    for (int j = 0; j < SL; ++j) {
+                        const uint32_t off = (uint32_t)(kr[j] - c0);
+                        if (kr[j] != -1 && off < (uint32_t)span) atomicOr(&rw[off >> 5].x, 1u << (off & 31));
                     }
                     __syncthreads();
                     const int S = (nw + G - 1) / G;
@@ -996,20 +1007,34 @@ __global__ __launch_bounds__(G) void k_num_hash(const NumRow *__restrict__ rows,
                             pre += __popc(rw[w0 + j].x);
                         }
                     __syncthreads();
-                    for (int s = tid; s < T; s += G) {
-                        const int k = keys[s];
-                        const uint32_t off = (uint32_t)(k - c0);
-                        if (k != -1 && off < (uint32_t)span) {
+#pragma unroll
+                    for (int j = 0; j < SL; ++j) {
+                        const uint32_t off = (uint32_t)(kr[j] - c0);
+                        if (kr[j] != -1 && off < (uint32_t)span) {
                             const uint2 e = rw[off >> 5];
-                            const int r = (int)(e.y + __popc(e.x & ((1u << (off & 31)) - 1u)));
-                            if (r < expected) {
-                                cC[o + r] = k;
-                                vC[o + r] = vals[s];
-                            }
+                            rk[j] = (int)(e.y + __popc(e.x & ((1u << (off & 31)) - 1u)));
                         }
                     }
                     base += total;
                     __syncthreads();                          // the bitmap is reused by the next pass
+                }
+                // ranks are a permutation of [0, base), base <= T: every entry
+                // is read before any moves
+                V vr[SL];
+#pragma unroll
+                for (int j = 0; j < SL; ++j) vr[j] = vals[j * G + tid];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < SL; ++j)
+                    if (rk[j] >= 0) {
+                        keys[rk[j]] = kr[j];
+                        vals[rk[j]] = vr[j];
+                    }
+                __syncthreads();
+                const int n = base < expected ? base : expected;
+                for (int i = tid; i < n; i += G) {
+                    __builtin_nontemporal_store(keys[i], &cC[o + i]);
+                    __builtin_nontemporal_store(vals[i], &vC[o + i]);
                 }
                 if (base != expected && tid == 0) atomicOr(&wh->err, ERR_COUNT);
                 ranked = true;
