@@ -397,47 +397,6 @@ __device__ __forceinline__ void enum_row(int a0, int a1, const int32_t *__restri
     }
 }
 
-// Exclusive in-place bitonic sort (ascending keys) of n <= np2 entries held in
-// LDS, all compare-exchanges oriented low-to-high so that positions >= n
-// behave as +infinity and need no storage.
-template <int G, typename V>
-__device__ void bitonic_sort_lds(int *keys, V *vals, int n) {
-    if (n <= 1) return;
-    int lg = 0;
-    while ((1 << lg) < n) ++lg;
-    const int half_total = 1 << (lg - 1);
-    for (int s = 1; s <= lg; ++s) {
-        const int hs = s - 1;                  // log2(half block)
-        for (int t = threadIdx.x; t < half_total; t += G) {
-            const int blk = t >> hs, o = t & ((1 << hs) - 1);
-            const int i = (blk << s) + o;
-            const int j = (blk << s) + (1 << s) - 1 - o;
-            if (j < n) {
-                const int ki = keys[i], kj = keys[j];
-                if (ki > kj) {
-                    keys[i] = kj; keys[j] = ki;
-                    const V vi = vals[i]; vals[i] = vals[j]; vals[j] = vi;
-                }
-            }
-        }
-        block_sync<G>();
-        for (int ls = hs - 1; ls >= 0; --ls) {
-            for (int t = threadIdx.x; t < half_total; t += G) {
-                const int i = ((t >> ls) << (ls + 1)) + (t & ((1 << ls) - 1));
-                const int j = i + (1 << ls);
-                if (j < n) {
-                    const int ki = keys[i], kj = keys[j];
-                    if (ki > kj) {
-                        keys[i] = kj; keys[j] = ki;
-                        const V vi = vals[i]; vals[i] = vals[j]; vals[j] = vi;
-                    }
-                }
-            }
-            block_sync<G>();
-        }
-    }
-}
-
 // Sort the n <= T entries at the front of a T-slot table (distinct keys >= 0)
 // in one pass of bucketing: keys are spread over NB = T/2 buckets by their
 // place in [min, max] (a monotone map), the bucket counts are scanned, every
@@ -520,9 +479,17 @@ __device__ void bucket_sort_lds(int *keys, V *vals, int n) {
     for (int i = 0; i < E; ++i) {
         r[i] = -1;
         if (k[i] >= 0) {
+            // eight reads in flight: a skewed key set can put many keys in
+            // one bucket (R-MAT rows crowd their low columns)
             const int s0 = start[b[i]], s1 = s0 + cnt[b[i]];
-            int c = s0;
-            for (int q = s0; q < s1; ++q) c += keys[q] < k[i];
+            int c = s0, q = s0;
+            for (; q + 8 <= s1; q += 8) {
+                int t = 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t += keys[q + u] < k[i];
+                c += t;
+            }
+            for (; q < s1; ++q) c += keys[q] < k[i];
             r[i] = c;
         }
     }
@@ -564,8 +531,7 @@ __device__ __forceinline__ int compact_store(int *keys, V *vals, int *wsum, int6
     const int n = total < expected ? total : expected;
     if (total != expected && tid == 0) atomicOr(err, ERR_COUNT);
     if constexpr (SORTED) {
-        if constexpr (G < 512) bucket_sort_lds<G, T, V>(keys, vals, total);
-        else bitonic_sort_lds<G, V>(keys, vals, total);
+        bucket_sort_lds<G, T, V>(keys, vals, total);
     }
     for (int j = tid; j < n; j += G) {
         __builtin_nontemporal_store(keys[j], &colsC[out_pos + j]);
