@@ -860,11 +860,10 @@ __global__ __launch_bounds__(256) void k_entry_brow(int64_t nnz, const int32_t *
 
 // ----------------------------------------------------------------------- numeric
 
-// Column passes of the rank sort of a wide bin before it falls back to bitonic
-// sorting: a pass reads the whole table, so the limit grows with the table
-// (measured at 2^20 columns: 13 passes beat the bitonic network for 11264
-// slots and lose to it for 8192).
-__host__ __device__ constexpr int rank_passes(int T) { return T / 768 > 1 ? T / 768 : 1; }
+// Column passes of the rank sort of a wide bin before it falls back to the
+// bucket sort (measured at 2^20 columns, 13 passes: the 11264-slot bin took
+// 13.3 ms ranked and 10.6 ms bucket-sorted).
+__host__ __device__ constexpr int rank_passes(int) { return 2; }
 
 // LDS of a numeric hash block besides its table: the enumeration state, and
 // (512-thread bins) extra words so that the idle enumeration LDS plus them can
@@ -967,7 +966,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const NumRow *__restrict__ rows,
             // the entries then move to their ranks inside the table and leave
             // in coalesced runs (stores straight to scattered places of C cost
             // partial-line writes to HBM).  Up to rank_passes(T) passes; wider
-            // matrices sort by bitonic networks.
+            // matrices are bucket-sorted.
             constexpr int RW = (int)(sizeof(NumLds<G, V>) / sizeof(uint2));
             constexpr int64_t PW = (int64_t)RW * 32;
             constexpr int SL = T / G;                             // slots per thread
