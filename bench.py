@@ -736,6 +736,16 @@ def bench_batch(args, sp, dev, small_ops):
         step()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    # the same batch again through its captured launch graph (shapes repeat)
+    dt_replay = None
+    if not rest:
+        bt.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bt.replay()
+        torch.cuda.synchronize()
+        dt_replay = (time.perf_counter() - t0) / max(args.steps, 1)
     serial_products(reqs[:8])
     ts = min(serial_products(reqs) for _ in range(2))
     flop = sum(bt.flop)
@@ -750,6 +760,8 @@ def bench_batch(args, sp, dev, small_ops):
         "serial_ms": round(ts * 1e3, 3),
         "speedup_vs_serial": round(ts / dt, 2),
         "speedup_incl_analyse": round(ts / (dt + t_analyse), 2),
+        "graph_replay_ms": None if dt_replay is None else round(dt_replay * 1e3, 3),
+        "speedup_graph_replay": None if dt_replay is None else round(ts / dt_replay, 2),
     }
     print(json.dumps(out), flush=True)
 

@@ -406,6 +406,7 @@ class Batch:
         self.arena = None
         self.results = None
         self.status: List[int] = []
+        self._graph = None
         if allocate:
             self.allocate()
 
@@ -436,6 +437,26 @@ class Batch:
                                    self.arena_bytes, ctypes.c_void_p(self.results.data_ptr()),
                                    _stream_handle(stream if stream is not None else self.stream))
         _check(st, "spgemm_batch_run")
+
+    def replay(self, stream=None):
+        """Run the batch by replaying a HIP graph of its launch sequence,
+        captured on the first call: the sequence is fixed while the batch's
+        structure is (operand values may change between replays), so a batch
+        of the same shapes run again costs one graph launch instead of some
+        thirty kernel launches.  The arena, results and scratch stay put."""
+        if self.arena is None:
+            raise SpgemmError(-6, "Batch.replay: arena not allocated")
+        s = _on_stream(stream if stream is not None else self.stream)
+        if self._graph is None:
+            cap = torch.cuda.Stream(device=self.device)
+            cap.wait_stream(s)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                self.run(stream=cap)
+            s.wait_stream(cap)
+            self._graph = g
+        with torch.cuda.stream(s):
+            self._graph.replay()
 
     def outputs(self) -> List[Optional[DeviceCSR]]:
         """Per-product results as DeviceCSR views into the arena (None where the

@@ -244,7 +244,7 @@ class Server:
         self.gate.release(sb)
         if not small:
             return
-        est = [24 * bounds[i] + 8 * (reqs[i].A.nrows + 1) + 1280 for i in small]
+        est = [12 * bounds[i] + 8 * (reqs[i].A.nrows + 1) + 768 for i in small]
         fixed = batch_scratch_bytes([As[i] for i in small])
         for g in split_to_budget(est, self.gate.budget, fixed):
             sub = [reqs[small[j]] for j in g]

@@ -116,6 +116,25 @@ def test_batch_graph_replay(sp):
         del junk
 
 
+def test_batch_replay_api(sp):
+    """Batch.replay(): the captured launch sequence replayed after the operand
+    values change (structure fixed) gives the product of the new values."""
+    import torch
+    _note("case batch replay api")
+    pairs, flags = _mixed_products(16, 7)
+    dev = [(sp.DeviceCSR.from_host(a), sp.DeviceCSR.from_host(b)) for a, b in pairs]
+    bt = sp.Batch([x for x, _ in dev], [y for _, y in dev], flags)
+    for rep in range(3):
+        scale = float(rep + 1)
+        for (a, b), (_, db) in zip(pairs, dev):
+            db.vals.copy_(torch.from_numpy(b.vals * scale).to(db.vals.device))
+        bt.replay()
+        torch.cuda.synchronize()
+        for (a, b), f, C in zip(pairs, flags, bt.outputs()):
+            b2 = type(b)(b.nrows, b.ncols, b.rpts, b.cols, b.vals * scale)
+            assert_matches(C, oracle.spgemm(a, b2, sorted_output=f), f)
+
+
 def _row_major(rp, cl, vl, srt):
     """Columns and values of a product; unsorted rows (whose order depends on
     which thread claimed each table slot) are put in column order first."""
