@@ -113,9 +113,9 @@ def test_plan_row_flop_is_fig4(sp):
 
 @pytest.mark.parametrize("degenerate", [False, True])
 def test_collision_factor_counters(sp, degenerate):
-    """Probe counters (SPGEMM_PROBE_COUNT): every insertion reads at least one
-    bucket, so probes >= flop per bin; under the hash that sends every key to
-    bucket 0, probes grow like the square of the keys per row."""
+    """Probe counters (SPGEMM_PROBE_COUNT): every insertion makes at least one
+    LDS probe, so probes >= flop per bin; under the hash that sends every key
+    to bucket 0, probes grow like the square of the keys per row."""
     import torch
     _note(f"case probe counters degenerate={degenerate}")
     A = rmat(12, 8, 6)
