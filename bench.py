@@ -393,9 +393,11 @@ def cpu_baseline(inp, seconds, srt, seed):
     nrows, flop, dt = n1 + n2, fl1 + fl2, t1 + t2
     passes = 1
     if nrows >= A.nrows:
-        # the whole product took less than the target: repeat it
+        # the whole product took less than the target: repeat it while one
+        # more pass still fits the target
         total = int(csum[-1])
-        while dt < seconds:
+        per = dt
+        while dt + per <= seconds:
             t0 = time.perf_counter()
             C = oracle.spgemm(A, B, sorted_output=srt, validate_inputs=False)
             dt += time.perf_counter() - t0
