@@ -58,7 +58,7 @@ enum {
                                   ids in range); failure gives SPGEMM_ERR_INVALID_CSR */
     SPGEMM_TIMING = 1u << 2,   /* record HIP events around every kernel launch from
                                   the plan on (see spgemm_plan_kernel_times)        */
-    SPGEMM_PROBE_COUNT = 1u << 4, /* count the bucket reads of every hash-table
+    SPGEMM_PROBE_COUNT = 1u << 4, /* count the LDS probes of every hash-table
                                   insertion per bin (spgemm_stats: the collision
                                   factor of Eq. 2); a debugging aid, not free   */
     SPGEMM_LOW_MEMORY = 1u << 3 /* do not keep the symbolic bitmaps of rows whose
@@ -130,7 +130,9 @@ size_t spgemm_plan_scratch_bytes(int nprod, const spgemm_csr *A);
  * worst case, for tests).  bucket_slots (4, 8 or 16) is the width of the
  * tables' buckets: a key's bucket is scanned 4 slots (one 16-byte LDS load)
  * at a time, front to back, and a full bucket passes the probe to the next;
- * 8 and 16 are the wider chunks of the HashVector variant (Section 4.2.2).
+ * with 4-slot buckets an insertion first tries the key's own slot of its
+ * bucket with one compare-and-swap.  8 and 16 are the wider chunks of the
+ * HashVector variant (Section 4.2.2).
  * heap = 1 selects the Heap accumulator of Section 4.2.3 for the numeric
  * phase of every row whose output fits an LDS table, that has at most 256
  * entries of A and at most 1024 products: the row is merged from the sorted
@@ -227,7 +229,8 @@ typedef struct {
     int64_t probe_overflow;  /* must be 0: hash probes that exceeded the table size */
     int64_t heap_rows;       /* rows whose numeric phase took the heap merge        */
     /* Collision factor of Eq. 2 per LDS table bin b = 1..9 (index b-1):
-     * c = probes / flop, the 16-byte bucket reads per insertion.  probes are
+     * c = probes / flop, the LDS probes per insertion (a compare-and-swap on the
+ * key's own slot, then each 16-byte bucket read).  probes are
      * counted only in plans made with SPGEMM_PROBE_COUNT (else 0); flop is
      * the bin's multiplications (symbolic bins by key bound, numeric bins by
      * nnz(c_i); valid after spgemm_symbolic). */
