@@ -163,7 +163,7 @@ int spgemm_batch_analyse(int nprod, const spgemm_csr *A, void *scratch, int64_t 
     if (e != hipSuccess) return SPGEMM_ERR_HIP;
     for (int p = 0; p < nprod; ++p) {
         flop[p] = (int64_t)h[p];
-        // a product with a row out of range takes no staging (its rows are skipped)
+        // a product with a row out of range takes no arena (its rows are skipped)
         bound[p] = h[2 * nprod + p] > (unsigned long long)BATCH_XMAX ? 0 : (int64_t)h[nprod + p];
         if (max_key) max_key[p] = (int64_t)h[2 * nprod + p];
     }

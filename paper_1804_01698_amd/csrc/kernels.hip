@@ -957,7 +957,7 @@ __global__ __launch_bounds__(G) void k_num_hash(const NumRow *__restrict__ rows,
         const int expected = (int)(nr.out_n & 0xFFFFu);
         bool ranked = false;
         if constexpr (SORTED && G >= 512) {
-            // Sorted output of a wide bin by rank instead of a bitonic sort: the
+            // Sorted output of a wide bin by rank instead of a bucket sort: the
             // columns of C are swept in passes of as many columns as a bitmap in
             // the (now idle) enumeration LDS holds; in a pass, the keys inside
             // it set their bit, and an exclusive popcount prefix per word plus

@@ -5,8 +5,8 @@ share the GPU, each on a stream of its own:
 
 * the batch worker takes every request queued when it becomes free and
   analyses them together (row flop and key bounds of every row, Fig. 4).
-  Products whose rows all fit the batched LDS tables and whose one-phase
-  upper-bound arena is small run as one batch; products with a row outside
+  Products whose rows all fit the batched LDS tables and whose arena
+  (sized from the rows' upper bounds) is small run as one batch; products with a row outside
   that range, more than ``batch_flop_max`` multiplications or an upper-bound
   arena above an eighth of the budget go to the plan worker;
 * the plan worker runs those products one at a time through the two-phase
