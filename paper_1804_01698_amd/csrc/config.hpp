@@ -41,9 +41,13 @@ constexpr int BM_WORDS_LARGE = 36864;   // 144 KB: 1,179,648 columns
 // 512-slot tables (one wave per row): the rows there are latency-bound chains
 // of dependent loads, and narrower blocks keep more rows in flight per CU
 // (ER 2^20, 256 products per row: 6.7 -> 4.9 ms against 128-thread blocks).
+// The same holds up to the 8192-slot table, whose 512-thread blocks fit four
+// rows per CU in LDS (R-MAT scale 20: 0.93 -> 0.71 ms against 1024 threads;
+// 4096 slots with 256 threads 0.37 -> 0.25 ms, 2048 slots with 128 threads
+// 0.20 -> 0.16 ms); the 16384-slot table keeps two 1024-thread rows per CU.
 constexpr int NSB = 11;
 constexpr int SYM_BITMAP_BIN = 10;
-constexpr int SYM_G[NSB] = {0, 64, 64, 64, 64, 128, 256, 512, 1024, 1024, 1024};
+constexpr int SYM_G[NSB] = {0, 64, 64, 64, 64, 128, 128, 256, 512, 1024, 1024};
 constexpr int SYM_T[NSB] = {0, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 0};
 constexpr int64_t SYM_XMAX[NSB] = {0, 32, 64, 128, 256, 512, 1024, 2048, 4096, WIN_CAP, INT64_MAX};
 
