@@ -161,7 +161,9 @@ int spgemm_config_check(const spgemm_config *cfg);
 /*
  * Plan nprod independent products C[p] = A[p]*B[p] (nprod >= 1; A and B are
  * host arrays of nprod descriptors).  Computes row flop and groups rows by
- * flop on the device, then reads the group sizes back (synchronises stream).
+ * flop on the device (Section 4.1 and Fig. 4: the flop of every row, then the
+ * rows grouped so that each group's table fits its largest row), then reads
+ * the group sizes back (synchronises stream).
  *   plan_scratch     device buffer of spgemm_plan_scratch_bytes(nprod, A)
  *                    bytes, kept alive until spgemm_free
  *   workspace_bytes  out: bytes of device workspace spgemm_symbolic needs
@@ -212,7 +214,8 @@ int spgemm_symbolic_static(spgemm_plan_t plan, int64_t *const *rpts_C, int64_t *
 int spgemm_numeric(spgemm_plan_t plan, const spgemm_csr *A, const spgemm_csr *B,
                    int32_t *const *cols_C, void *const *vals_C);
 
-/* Release the plan's host state (device buffers stay the caller's).  NULL-safe. */
+/* Release the plan's host state (device buffers stay the caller's).  NULL-safe.
+ * Bookkeeping of this interface only: no passage of the paper defines it. */
 int spgemm_free(spgemm_plan_t plan);
 
 /* Static text for a status code (the HIP message for SPGEMM_ERR_HIP is that of
