@@ -415,7 +415,7 @@ int spgemm_symbolic(spgemm_plan_t pl, void *workspace, int64_t *const *rpts_C, i
                                 return launch_sym_segments(nr, perm, off.v[b], q.A, Bb, q.nchunks,
                                                            q.at<uint32_t>(q.o_chunk), nnz,
                                                            q.store_bm ? q.at<uint32_t>(q.o_bmap) : nullptr,
-                                                           pl->ncu, s);
+                                                           q.wh, pl->ncu, s);
                             }),
                       "sym_bitmap");
             } else {
@@ -508,6 +508,10 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
         q.A.vals = A[p].vals;
         q.B.vals = B[p].vals;
         const unsigned nitems = q.hw.n_items;
+        // claim counters of the windows and of the persistent hash bins
+        bool claims = nitems > 0;
+        for (int b = 1; b < NUM_HEAVY_BIN; ++b) claims |= NUM_G[b] >= 512 && q.hw.num_rows[b] > 0;
+        if (claims) HIPCK(launch_num_reset(q.wh, s), "num_reset");
         if (nitems > 0) {
             HIPCK(timed(pl, "gather_B_vals", 20.0 * q.B.nnz,
                         [&] {

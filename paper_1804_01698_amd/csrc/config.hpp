@@ -185,10 +185,16 @@ struct WsHdr {
     int err;
     unsigned int probe_overflow;
     unsigned int n_groups;
-    unsigned int pad2_[2];
+    unsigned int bm_next;       // row claim counter of the bitmap bin (k_sym_bitmap)
+    unsigned int pad2_;
     unsigned int win_next[8];   // window claim counters, one per XCD group
     unsigned long long sym_probes[NSB];   // bucket reads of the hash inserts (SPGEMM_PROBE_COUNT)
     unsigned long long num_probes[NNB];
+    // row claim counters of the persistent hash bins, per bin: the symbolic
+    // ones start at zero with the header, the numeric ones are reset at the
+    // start of every numeric phase (k_num_reset)
+    unsigned int sym_next[NSB];
+    unsigned int num_next[NNB];
 };
 
 // One column window of one heavy row.

@@ -326,11 +326,16 @@ __global__ __launch_bounds__(G) __attribute__((amdgpu_waves_per_eu(8))) void k_s
                                                 int32_t *__restrict__ nnz_row, WsHdr *wh, HashCfg hc) {
     __shared__ __align__(16) int tab[T];
     __shared__ SegLds<G, false, double> sg;
+    __shared__ unsigned s_next;
     const int tid = threadIdx.x;
     // persistent over the bin's rows, or one row per block (a single trip)
-    const unsigned step = PERSIST ? gridDim.x : nrows;
     unsigned it = blockIdx.x;
     if (it >= nrows) return;                              // uniform over the block
+    // persistent: each block's first two rows are blockIdx.x and blockIdx.x +
+    // gridDim.x, later ones are claimed from the bin's counter (a fixed stride
+    // leaves blocks with unequal work when the bin holds few rows per block);
+    // thread 0 issues the claim of the row after next at the top of each row
+    unsigned pend = it + gridDim.x;
     // the bin list gives the row and its A range side by side (no dependent load)
     RowPre<double> cur;
     {
@@ -341,8 +346,12 @@ __global__ __launch_bounds__(G) __attribute__((amdgpu_waves_per_eu(8))) void k_s
     while (true) {
         const int row = cur.row;
         table_clear<G, T, false, double>(tab, nullptr);
+        if (PERSIST && tid == 0) {
+            s_next = pend;
+            pend = 2 * gridDim.x + atomicAdd(&wh->sym_next[hc.bin], 1u);
+        }
         __syncthreads();
-        const unsigned nit = it + step;
+        const unsigned nit = PERSIST ? s_next : nrows;
         RowPre<double> nxt{};
         if constexpr (PERSIST)
             if (nit < nrows) {
@@ -409,7 +418,7 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
                                                      const int32_t *__restrict__ cB, int64_t ncols,
                                                      int nchunks, uint32_t *__restrict__ chunk_cnt,
                                                      int32_t *__restrict__ nnz_row,
-                                                     uint32_t *__restrict__ bmap) {
+                                                     uint32_t *__restrict__ bmap, WsHdr *wh) {
     constexpr int G = 1024;
     constexpr int64_t WIN = (int64_t)NWORDS * 32;
     constexpr int Q_PER_CHUNK = WORDS_PER_CHUNK / 4;          // 16-byte quads per chunk
@@ -418,10 +427,18 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
     __shared__ __align__(16) uint32_t bm[NWORDS];
     __shared__ SegLds<G, false, double> sg;
     __shared__ int s_total;
+    __shared__ unsigned s_next;
     u32x4 *bm4 = reinterpret_cast<u32x4 *>(bm);
     const int tid = threadIdx.x;
     unsigned slot = blockIdx.x;                               // the row's index in the bin
     if (slot >= nrows) return;                                // uniform over the block
+    // Each block's first two rows are blockIdx.x and blockIdx.x + gridDim.x;
+    // later rows are claimed one at a time from a counter (row flop in this
+    // bin spans three orders of magnitude, so a fixed stride leaves some
+    // blocks with far more work than others).  Thread 0 issues the claim of
+    // the row after next at the top of each row, so its latency hides behind
+    // a whole row.
+    unsigned pend = slot + gridDim.x;
     // the bitmap is clear at the start of every pass: cleared once here, then
     // by the last phase that reads it
     for (int i = tid; i < NWORDS / 4; i += G) bm4[i] = u32x4{0u, 0u, 0u, 0u};
@@ -434,10 +451,14 @@ __global__ __launch_bounds__(1024) void k_sym_bitmap(const int32_t *__restrict__
     auto slice = [&](int k, int &lo, int &hi) { lo = rB[k]; hi = rB[k + 1]; };
     while (true) {
         const int row = cur.row;
-        if (tid == 0) s_total = 0;
+        if (tid == 0) {
+            s_total = 0;
+            s_next = pend;
+            pend = 2 * gridDim.x + atomicAdd(&wh->bm_next, 1u);
+        }
         __syncthreads();
         // the next row's A entries are loaded while this row's products run
-        const unsigned nslot = slot + gridDim.x;
+        const unsigned nslot = s_next;
         RowPre<double> nxt{};
         if (nslot < nrows) {
             const int r1 = perm[perm_off + nslot];
@@ -888,11 +909,15 @@ __global__ __launch_bounds__(G) void k_num_hash(const NumRow *__restrict__ rows,
     __shared__ __align__(16) NumLds<G, V> lds;
     __shared__ int rank_ws[G / WAVE + 1];
     SegLds<G, true, V> &sg = lds.sg;
+    __shared__ unsigned s_next;
     const int tid = threadIdx.x;
-    // persistent over the bin's rows, or one row per block (a single trip)
-    const unsigned step = PERSIST ? gridDim.x : nrows;
+    // persistent over the bin's rows (the first two blockIdx.x and blockIdx.x
+    // + gridDim.x, later ones claimed from the bin's counter, the claim of the
+    // row after next issued at the top of each row), or one row per block (a
+    // single trip)
     unsigned it = blockIdx.x;
     if (it >= nrows) return;                                  // uniform over the block
+    unsigned pend = it + gridDim.x;
     // the bin list gives each row's A range and place in C (no dependent load);
     // RowPre.row carries the list index
     NumRow nr = rows[perm_off + it];
@@ -901,9 +926,13 @@ __global__ __launch_bounds__(G) void k_num_hash(const NumRow *__restrict__ rows,
     else cur = RowPre<V>{(int)it, nr.a0, nr.a1, -1, 0, 0, V(0)};
     while (true) {
         table_clear<G, T, true, V>(keys, vals);
+        if (PERSIST && tid == 0) {
+            s_next = pend;
+            pend = 2 * gridDim.x + atomicAdd(&wh->num_next[hc.bin], 1u);
+        }
         __syncthreads();
         // the next row's A entries are loaded while this row's products run
-        const unsigned nit = it + step;
+        const unsigned nit = PERSIST ? s_next : nrows;
         RowPre<V> nxt{};
         NumRow nnr{};
         if constexpr (PERSIST)
@@ -1802,24 +1831,25 @@ hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, const in
 // persistent: a grid of the blocks that fit the CUs at once walks the bin
 template <int W>
 static void sym_bitmap_l(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                         int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, int ncu, hipStream_t s) {
+                         int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, WsHdr *wh, int ncu,
+                         hipStream_t s) {
     static const int occ = blocks_per_cu(k_sym_bitmap<W>, 1024);
     const unsigned grid = (unsigned)std::min<int64_t>(nbm, (int64_t)ncu * occ);
     k_sym_bitmap<W><<<grid, 1024, 0, s>>>(perm, off, nbm, A.rpts, A.cols, B.rpts, B.cols, B.ncols, nchunks, chunk_cnt,
-                                          nnz_row, bmap);
+                                          nnz_row, bmap, wh);
 }
 
 hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, int ncu,
-                               hipStream_t s) {
+                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, WsHdr *wh,
+                               int ncu, hipStream_t s) {
     if (nbm == 0) return hipSuccess;
     const int64_t need = (B.ncols + 31) / 32;
     if (need <= BM_WORDS_SMALL)
-        sym_bitmap_l<BM_WORDS_SMALL>(nbm, perm, off, A, B, nchunks, chunk_cnt, nnz_row, bmap, ncu, s);
+        sym_bitmap_l<BM_WORDS_SMALL>(nbm, perm, off, A, B, nchunks, chunk_cnt, nnz_row, bmap, wh, ncu, s);
     else if (need <= BM_WORDS_MID)
-        sym_bitmap_l<BM_WORDS_MID>(nbm, perm, off, A, B, nchunks, chunk_cnt, nnz_row, bmap, ncu, s);
+        sym_bitmap_l<BM_WORDS_MID>(nbm, perm, off, A, B, nchunks, chunk_cnt, nnz_row, bmap, wh, ncu, s);
     else
-        sym_bitmap_l<BM_WORDS_LARGE>(nbm, perm, off, A, B, nchunks, chunk_cnt, nnz_row, bmap, ncu, s);
+        sym_bitmap_l<BM_WORDS_LARGE>(nbm, perm, off, A, B, nchunks, chunk_cnt, nnz_row, bmap, wh, ncu, s);
     return hipGetLastError();
 }
 
@@ -1940,13 +1970,25 @@ __global__ void k_zero_u32n(unsigned *p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
 
+// Claim counters of the numeric phase (windows and persistent hash bins) back
+// to zero: the phase may run again on the same symbolic result.
+__global__ void k_num_reset(WsHdr *wh) {
+    const int t = (int)threadIdx.x;
+    if (t < 8) wh->win_next[t] = 0u;
+    if (t < NNB) wh->num_next[t] = 0u;
+}
+
+hipError_t launch_num_reset(WsHdr *wh, hipStream_t s) {
+    k_num_reset<<<1, 64, 0, s>>>(wh);
+    return hipGetLastError();
+}
+
 
 // Windows leave in ascending column order, so sorted and unsorted output share it.
 hipError_t launch_num_window(int dtype, unsigned nitems, const WinItem *items, const CsrDev &A, const int2 *ki,
                              const int32_t *idx, int nchunks, const int32_t *bc, const void *bv, int32_t *cC,
                              void *vC, const uint32_t *bmap, WsHdr *wh, int ncu, hipStream_t s) {
     if (nitems == 0) return hipSuccess;
-    k_zero_u32n<<<1, 64, 0, s>>>(wh->win_next, 8);
     if (dtype == 0) {
         static const int occ = blocks_per_cu(k_num_window<double>, WIN_G);
         const unsigned grid = (unsigned)std::min<int64_t>(nitems, (int64_t)ncu * occ);

@@ -30,10 +30,11 @@ hipError_t launch_sym_scatter(int m, const uint32_t *flop, const int32_t *rA, in
 hipError_t launch_sym_bin(int bin, unsigned nrows, const int32_t *perm, const int2 *prow, int64_t off, const CsrDev &A,
                           const CsrDev &B, int32_t *nnz_row, WsHdr *wh, HashCfg hc, int ncu, hipStream_t s);
 hipError_t launch_sym_segments(unsigned nbm, const int32_t *perm, int64_t off, const CsrDev &A, const CsrDev &B,
-                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, int ncu,
-                               hipStream_t s);
+                               int nchunks, uint32_t *chunk_cnt, int32_t *nnz_row, uint32_t *bmap, WsHdr *wh,
+                               int ncu, hipStream_t s);
 hipError_t launch_scan(const int32_t *nnz_row, int m, long long *bsum, int64_t *rpts_C, WsHdr *wh,
                        hipStream_t s);
+hipError_t launch_num_reset(WsHdr *wh, hipStream_t s);
 hipError_t launch_num_hist(int m, const int32_t *nnz_row, const uint32_t *flop, const int32_t *rA,
                            const int32_t *slot_of, HeavyRow *heavy, WsHdr *wh, const BinLimits &L, hipStream_t s);
 hipError_t launch_count_long_b(const CsrDev &B, PlanHdr *hdr, hipStream_t s);
