@@ -109,7 +109,9 @@ typedef struct spgemm_plan_s *spgemm_plan_t;
 /*
  * Bytes of device "plan scratch" spgemm_plan needs for nprod products whose
  * left operands are A[0..nprod-1] (a small header, 4 bytes per row of A for
- * the row flop and a list of the rows of A longer than 4096 entries).
+ * the row flop and lists of the rows of A longer than 32 entries: 4 bytes
+ * for each of at most min(rows, nnz / 33) of them and for each of at most
+ * nnz / 4097 rows longer than 4096 entries).
  * Returns 0 if an argument is invalid.
  */
 size_t spgemm_plan_scratch_bytes(int nprod, const spgemm_csr *A);

@@ -140,9 +140,14 @@ bool limits_from(const spgemm_config *cfg, BinLimits *L) {
     return true;
 }
 
-// header, per-row flop (uint32), per-entry B row length (uint32, plan time only)
+// header, per-row flop (uint32), the list of rows longer than FLOP_WAVE_ROW,
+// the list of rows of FLOP_SHORT_ROW+1 .. FLOP_WAVE_ROW entries (int32 each)
+static size_t huge_list_bytes(int64_t nnz) { return align_up((size_t)(nnz / (FLOP_WAVE_ROW + 1)) * 4); }
+static size_t long_list_bytes(int64_t m, int64_t nnz) {
+    return align_up((size_t)std::min<int64_t>(m, nnz / (FLOP_SHORT_ROW + 1)) * 4);
+}
 size_t plan_scratch_one(int64_t m, int64_t nnz) {
-    return PLAN_HDR_BYTES + align_up((size_t)m * 4) + align_up((size_t)(nnz / (FLOP_WAVE_ROW + 1)) * 4);
+    return PLAN_HDR_BYTES + align_up((size_t)m * 4) + huge_list_bytes(nnz) + long_list_bytes(m, nnz);
 }
 
 // Workspace of spgemm_symbolic_static.  Each GPU the library runs on holds
@@ -288,8 +293,10 @@ int spgemm_plan(spgemm_plan_t *out, int nprod, const spgemm_csr *A, const spgemm
     for (int p = 0; p < nprod; ++p) {
         Prod &q = pl->prods[p];
         int32_t *huge = (int32_t *)(q.ps + PLAN_HDR_BYTES + align_up((size_t)q.m * 4));   // after the row flop
-        hipError_t e = timed(pl, "row_flop", 12.0 * q.A.nnz + 8.0 * q.m,
-                             [&] { return launch_row_flop(q.A, q.B, q.flop, huge, q.phdr, pl->lim, stream); });
+        int32_t *longl = (int32_t *)((char *)huge + huge_list_bytes(q.A.nnz));
+        hipError_t e = timed(pl, "row_flop", 12.0 * q.A.nnz + 8.0 * q.m, [&] {
+            return launch_row_flop(q.A, q.B, q.flop, longl, huge, q.phdr, pl->lim, pl->ncu, stream);
+        });
         if (e == hipSuccess) e = launch_count_long_b(q.B, q.phdr, stream);
         if (e == hipSuccess && pl->lim.heap) e = launch_check_sorted(q.B, &q.phdr->err, stream);
         if (e != hipSuccess) return fail(hip_fail(e, "row_flop"));

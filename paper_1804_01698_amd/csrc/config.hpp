@@ -163,12 +163,16 @@ struct PlanHdr {
     unsigned long long sym_nnza[NSB];
     int err;
     unsigned n_huge;               // rows of A longer than FLOP_WAVE_ROW (listed for k_huge_flop)
-    int pad_[6];
+    unsigned n_long_a;             // rows of A of FLOP_SHORT_ROW+1 .. FLOP_WAVE_ROW entries (k_long_flop)
+    int pad_[5];
 };
 
-// Row flop: rows of A with more than FLOP_WAVE_ROW entries are summed by a
-// block of their own after the pass over all rows; the plan scratch lists
-// them (at most nnz(A) / (FLOP_WAVE_ROW + 1) rows).
+// Row flop: a row of A with at most FLOP_SHORT_ROW entries is summed by one
+// thread in the pass over all rows; longer rows are listed in the plan
+// scratch and summed after it, a wave per row up to FLOP_WAVE_ROW entries
+// (at most min(m, nnz(A) / (FLOP_SHORT_ROW + 1)) rows) and a block per row
+// beyond (at most nnz(A) / (FLOP_WAVE_ROW + 1) rows).
+constexpr int FLOP_SHORT_ROW = 32;
 constexpr int FLOP_WAVE_ROW = 4096;
 
 struct WsHdr {

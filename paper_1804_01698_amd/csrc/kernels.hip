@@ -58,12 +58,14 @@ __global__ __launch_bounds__(256) void k_validate(int64_t nrows, int64_t ncols, 
 
 // ----------------------------------------------------------------------- row flop
 
-// Row flop in two steps.  First every entry a_ik of A gets the length of B
-// row k (a flat, fully parallel gather).  Then 256 consecutive rows per
-// block: a row of at most 64 entries is summed by its own thread (contiguous
-// reads); longer rows (the hub rows of skewed inputs) are summed by the whole
-// block in turn, so no block waits on a long chain of dependent loads.
-constexpr int FLOP_SHORT_ROW = 32;
+// Row flop: the flop of row i is the sum over its entries a_ik of the length
+// of B row k.  A first pass takes 256 consecutive rows per block and sums a
+// row of at most FLOP_SHORT_ROW entries in its own thread (eight entries'
+// loads in flight); longer rows are listed and summed afterwards across the
+// whole GPU (k_long_flop: a wave per row; k_huge_flop: a block per row).
+// Summing them inside the first pass left the few row blocks where the long
+// rows of a skewed matrix crowd together walking dozens of rows per wave
+// while every other block had finished.
 
 // Length of the B row that entry p of A selects.
 __device__ __forceinline__ uint32_t entry_deg(int p, const int32_t *__restrict__ cA, const int32_t *__restrict__ rB) {
@@ -88,17 +90,17 @@ __device__ __forceinline__ void row_flop_put(int row, unsigned long long f, int 
 __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restrict__ rA,
                                                   const int32_t *__restrict__ cA, const int32_t *__restrict__ rB,
                                                   int64_t ncolsB, uint32_t *__restrict__ flop_out,
-                                                  int32_t *__restrict__ huge, PlanHdr *hdr, BinLimits L) {
-    __shared__ unsigned long long s_f[256];
-    __shared__ int s_long[256];
-    __shared__ int s_nlong;
+                                                  int32_t *__restrict__ longl, int32_t *__restrict__ huge,
+                                                  PlanHdr *hdr, BinLimits L) {
+    __shared__ int s_long[256], s_huge[256];
+    __shared__ int s_nlong, s_nhuge, s_lbase, s_hbase;
     __shared__ unsigned long long s_rows[NSB], s_flop[NSB], s_nnza[NSB];
     __shared__ unsigned long long s_tot, s_max;
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * 256;
     const int nr = min(256, m - r0);
     if (tid < NSB) { s_rows[tid] = 0; s_flop[tid] = 0; s_nnza[tid] = 0; }
-    if (tid == 0) { s_tot = 0; s_max = 0; s_nlong = 0; }
+    if (tid == 0) { s_tot = 0; s_max = 0; s_nlong = 0; s_nhuge = 0; s_lbase = 0; s_hbase = 0; }
     __syncthreads();
     int a0 = 0, a1 = 0;
     unsigned long long f = 0;
@@ -114,34 +116,23 @@ __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restri
                 f += d;
             }
             for (; p < a1; ++p) f += entry_deg(p, cA, rB);
+        } else if (a1 - a0 <= FLOP_WAVE_ROW) {
+            s_long[atomicAdd(&s_nlong, 1)] = r0 + tid;
         } else {
-            s_long[atomicAdd(&s_nlong, 1)] = tid;
+            s_huge[atomicAdd(&s_nhuge, 1)] = r0 + tid;
         }
     }
-    s_f[tid] = f;
     __syncthreads();
-    // rows longer than FLOP_SHORT_ROW entries: one wave each, in steps of 64
-    // entries with four steps' loads in flight; rows longer than
-    // FLOP_WAVE_ROW go to the list of k_huge_flop (the heaviest rows of a
-    // skewed matrix often share a block, which would walk them in turn)
-    const int nlong = s_nlong;
-    const int w = tid >> 6, ln = tid & 63;
-    for (int j = w; j < nlong; j += 4) {               // uniform over the wave
-        const int t = s_long[j];
-        const int b0 = rA[r0 + t], b1 = rA[r0 + t + 1];
-        if (b1 - b0 > FLOP_WAVE_ROW) {
-            if (ln == 0) huge[atomicAdd(&hdr->n_huge, 1u)] = r0 + t;
-            continue;
-        }
-        unsigned long long g = 0;
-#pragma unroll 4
-        for (int p = b0 + ln; p < b1; p += 64) g += entry_deg(p, cA, rB);
-        g = wave_sum_u64(g);
-        if (ln == 0) s_f[t] = g;                       // a long row's own lane left 0 there
+    // the block's long rows join the lists with one global atomic per list
+    if (tid == 0) {
+        if (s_nlong) s_lbase = (int)atomicAdd(&hdr->n_long_a, (unsigned)s_nlong);
+        if (s_nhuge) s_hbase = (int)atomicAdd(&hdr->n_huge, (unsigned)s_nhuge);
     }
     __syncthreads();
-    if (tid < nr && a1 - a0 <= FLOP_WAVE_ROW)
-        row_flop_put(r0 + tid, s_f[tid], a1 - a0, ncolsB, flop_out, s_rows, s_flop, s_nnza, &s_tot, &s_max, L);
+    if (tid < s_nlong) longl[s_lbase + tid] = s_long[tid];
+    if (tid < s_nhuge) huge[s_hbase + tid] = s_huge[tid];
+    if (tid < nr && a1 - a0 <= FLOP_SHORT_ROW)
+        row_flop_put(r0 + tid, f, a1 - a0, ncolsB, flop_out, s_rows, s_flop, s_nnza, &s_tot, &s_max, L);
     __syncthreads();
     if (tid < NSB && s_rows[tid]) {
         atomicAdd(&hdr->sym_rows[tid], s_rows[tid]);
@@ -149,6 +140,44 @@ __global__ __launch_bounds__(256) void k_row_flop(int m, const int32_t *__restri
         atomicAdd(&hdr->sym_nnza[tid], s_nnza[tid]);
     }
     if (tid == 0) {
+        atomicAdd(&hdr->total_flop, s_tot);
+        atomicMax(&hdr->max_flop, s_max);
+    }
+}
+
+// The listed rows of FLOP_SHORT_ROW+1 .. FLOP_WAVE_ROW entries, a wave each
+// over the whole list (a persistent grid; wave j of the grid takes entries j,
+// j + waves, ...), 64-entry steps with four steps' loads in flight; the
+// per-bin totals are gathered per block and added to the header once.
+__global__ __launch_bounds__(256) void k_long_flop(const int32_t *__restrict__ rA, const int32_t *__restrict__ cA,
+                                                   const int32_t *__restrict__ rB, int64_t ncolsB,
+                                                   const int32_t *__restrict__ longl, uint32_t *__restrict__ flop_out,
+                                                   PlanHdr *hdr, BinLimits L) {
+    __shared__ unsigned long long s_rows[NSB], s_flop[NSB], s_nnza[NSB];
+    __shared__ unsigned long long s_tot, s_max;
+    const int tid = threadIdx.x;
+    if (tid < NSB) { s_rows[tid] = 0; s_flop[tid] = 0; s_nnza[tid] = 0; }
+    if (tid == 0) { s_tot = 0; s_max = 0; }
+    __syncthreads();
+    const unsigned n = hdr->n_long_a;
+    const unsigned nw = gridDim.x * 4;
+    const int ln = tid & 63;
+    for (unsigned j = blockIdx.x * 4 + (unsigned)(tid >> 6); j < n; j += nw) {   // uniform over the wave
+        const int row = longl[j];
+        const int b0 = rA[row], b1 = rA[row + 1];
+        unsigned long long g = 0;
+#pragma unroll 4
+        for (int p = b0 + ln; p < b1; p += 64) g += entry_deg(p, cA, rB);
+        g = wave_sum_u64(g);
+        if (ln == 0) row_flop_put(row, g, b1 - b0, ncolsB, flop_out, s_rows, s_flop, s_nnza, &s_tot, &s_max, L);
+    }
+    __syncthreads();
+    if (tid < NSB && s_rows[tid]) {
+        atomicAdd(&hdr->sym_rows[tid], s_rows[tid]);
+        atomicAdd(&hdr->sym_flop[tid], s_flop[tid]);
+        atomicAdd(&hdr->sym_nnza[tid], s_nnza[tid]);
+    }
+    if (tid == 0 && s_tot) {
         atomicAdd(&hdr->total_flop, s_tot);
         atomicMax(&hdr->max_flop, s_max);
     }
@@ -1778,11 +1807,17 @@ hipError_t launch_validate(const CsrDev &a, int *err, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, int32_t *huge, PlanHdr *hdr,
-                           const BinLimits &L, hipStream_t s) {
+hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, int32_t *longl, int32_t *huge,
+                           PlanHdr *hdr, const BinLimits &L, int ncu, hipStream_t s) {
     if (A.nrows == 0) return hipSuccess;
-    k_row_flop<<<grid1(A.nrows, 256), 256, 0, s>>>((int)A.nrows, A.rpts, A.cols, B.rpts, B.ncols, flop, huge, hdr,
-                                                    L);
+    k_row_flop<<<grid1(A.nrows, 256), 256, 0, s>>>((int)A.nrows, A.rpts, A.cols, B.rpts, B.ncols, flop, longl, huge,
+                                                    hdr, L);
+    // rows that can have more than FLOP_SHORT_ROW entries: four per block,
+    // at most eight blocks per CU
+    const int64_t cap_long = std::min<int64_t>(A.nrows, A.nnz / (FLOP_SHORT_ROW + 1));
+    if (cap_long > 0)
+        k_long_flop<<<(unsigned)std::min<int64_t>((cap_long + 3) / 4, (int64_t)ncu * 8), 256, 0, s>>>(
+            A.rpts, A.cols, B.rpts, B.ncols, longl, flop, hdr, L);
     const int64_t cap = A.nnz / (FLOP_WAVE_ROW + 1);   // rows that can be that long
     if (cap > 0)
         k_huge_flop<<<(unsigned)cap, 256, 0, s>>>(A.rpts, A.cols, B.rpts, B.ncols, huge, flop, hdr, L);

@@ -22,8 +22,8 @@ struct BinOffsets {
 
 
 hipError_t launch_validate(const CsrDev &a, int *err, hipStream_t s);
-hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, int32_t *huge, PlanHdr *hdr,
-                           const BinLimits &L, hipStream_t s);
+hipError_t launch_row_flop(const CsrDev &A, const CsrDev &B, uint32_t *flop, int32_t *longl, int32_t *huge,
+                           PlanHdr *hdr, const BinLimits &L, int ncu, hipStream_t s);
 hipError_t launch_sym_scatter(int m, const uint32_t *flop, const int32_t *rA, int64_t ncolsB, const BinOffsets &off,
                               int32_t *perm, int2 *prow, int32_t *nnz_row, int32_t *slot_of, WsHdr *wh,
                               const BinLimits &L, hipStream_t s);

@@ -85,9 +85,12 @@ def test_plan_scratch_bytes(lib):
     n = lib.spgemm_plan_scratch_bytes(2, arr)
     assert n >= 1000 * 4 and n % 256 == 0                 # header + row flop
     arr2 = (b._Csr * 2)(b._Csr(1000, 10, 700, 1, None, None), b._Csr(0, 10, 0, 1, None, None))
-    assert lib.spgemm_plan_scratch_bytes(2, arr2) == n    # no row can exceed 4096 entries
+    # 700 entries: at most 21 rows longer than 32 entries (one 256-byte slot
+    # for their list), none longer than 4096
+    assert lib.spgemm_plan_scratch_bytes(2, arr2) == n + 256
     arr3 = (b._Csr * 2)(b._Csr(1000, 10, 1 << 20, 1, None, None), b._Csr(0, 10, 0, 1, None, None))
-    assert lib.spgemm_plan_scratch_bytes(2, arr3) >= n + 4 * ((1 << 20) // 4097)   # list of long rows
+    # lists: every row may be longer than 32 entries, 255 rows longer than 4096
+    assert lib.spgemm_plan_scratch_bytes(2, arr3) == n + 4096 + 1024
     assert lib.spgemm_plan_scratch_bytes(0, arr) == 0
 
 
