@@ -111,6 +111,31 @@ def test_plan_row_flop_is_fig4(sp):
     p.close()
 
 
+def test_plan_row_flop_every_row_class(sp):
+    """Per-row flop on the device against the oracle for rows summed by a
+    thread (at most 32 entries), by a wave from the list of longer rows (up to
+    4096) and by a block from the list of the longest, several hundred of the
+    middle class so that the list spans many waves."""
+    _note("case plan row flop, every row class")
+    rng = np.random.default_rng(5)
+    nb = 50000
+    rows_b = [np.unique(rng.integers(0, 1 << 20, size=int(L))) for L in rng.integers(0, 41, size=nb)]
+    B = CSR(nb, 1 << 20, np.concatenate([[0], np.cumsum([len(r) for r in rows_b])]),
+            np.concatenate(rows_b).astype(np.int32), None)        # 0 to 40 entries per row
+    lens = np.concatenate([rng.integers(0, 33, size=3000), rng.integers(33, 4097, size=600),
+                           [0, 1, 32, 33, 4096, 4097, 10000, 40000]])
+    rng.shuffle(lens)
+    cols = np.concatenate([np.sort(rng.choice(nb, size=int(L), replace=False)) for L in lens])
+    A = CSR(len(lens), nb, np.concatenate([[0], np.cumsum(lens)]), cols.astype(np.int32), None)
+    A, B = with_values(A, 1, "f64"), with_values(B, 2, "f64")
+    dA, dB = sp.DeviceCSR.from_host(A, device="cuda"), sp.DeviceCSR.from_host(B, device="cuda")
+    p = sp.Plan([dA], [dB], sorted_output=False)
+    ref = oracle.row_flop(A, B).astype(np.int64)
+    assert np.array_equal(p.row_flop(0).astype(np.int64), ref)
+    assert p.stats(0)["flop"] == int(ref.sum())
+    p.close()
+
+
 @pytest.mark.parametrize("degenerate", [False, True])
 def test_collision_factor_counters(sp, degenerate):
     """Probe counters (SPGEMM_PROBE_COUNT): every insertion makes at least one
