@@ -515,7 +515,9 @@ int spgemm_numeric(spgemm_plan_t pl, const spgemm_csr *A, const spgemm_csr *B, i
         q.A.vals = A[p].vals;
         q.B.vals = B[p].vals;
         const unsigned nitems = q.hw.n_items;
-        // claim counters of the windows and of the persistent hash bins
+        // claim counters of the windows and of the persistent hash bins (the
+        // bins of 512 threads and up: the rule of num_hash_l, which launches
+        // them as persistent grids that claim rows)
         bool claims = nitems > 0;
         for (int b = 1; b < NUM_HEAVY_BIN; ++b) claims |= NUM_G[b] >= 512 && q.hw.num_rows[b] > 0;
         if (claims) HIPCK(launch_num_reset(q.wh, s), "num_reset");
